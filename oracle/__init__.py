@@ -1,0 +1,168 @@
+"""FP64 CPU oracle of kernelised linear global attention (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: only the tests, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg may import this package.  The product path
+never does.  The arithmetic lives in ``oracle.c``; this file only builds it
+and marshals numpy arrays.
+
+Array conventions: inputs are numpy arrays of shape [B, H, N, d] with the
+feature axis contiguous.  ``uint16`` arrays hold bfloat16 bit patterns;
+``float32`` and ``float64`` arrays hold their values.  Outputs are dense
+float64 arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with the host compiler (gcc, OpenMP)."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class _Tensor(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("sb", ctypes.c_int64), ("sh", ctypes.c_int64),
+                ("sn", ctypes.c_int64)]
+
+
+def use_library(path):
+    """Load the oracle from another build of oracle.c (the mutation tests
+    compile deliberately broken copies); returns the previous handle."""
+    global _lib
+    prev = _lib
+    _lib = None
+    _load(path)
+    return prev
+
+
+def restore_library(handle):
+    global _lib
+    _lib = handle
+
+
+def _load(path=None):
+    global _lib
+    if _lib is None:
+        if path is None and not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(path or _SO)
+        T = _Tensor
+        i64 = ctypes.c_int64
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_phi.restype = ctypes.c_double
+        lib.oracle_phi.argtypes = [ctypes.c_double]
+        lib.oracle_dphi.restype = ctypes.c_double
+        lib.oracle_dphi.argtypes = [ctypes.c_double]
+        lib.oracle_summary.argtypes = [i64, i64, i64, i64, T, T, dp, dp]
+        lib.oracle_apply.argtypes = [i64, i64, i64, i64, T, dp, dp, dp]
+        lib.oracle_forward.argtypes = [i64, i64, i64, i64, T, T, T, dp, dp, dp]
+        lib.oracle_backward.argtypes = [i64, i64, i64, i64, T, T, T, T,
+                                        dp, dp, dp, dp, dp]
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+_DTYPES = {np.dtype(np.uint16): 0, np.dtype(np.float32): 1,
+           np.dtype(np.float64): 2}
+
+
+def _tensor(a: np.ndarray) -> _Tensor:
+    if a.ndim != 4:
+        raise ValueError("expected a [B, H, N, d] array")
+    if a.dtype not in _DTYPES:
+        raise TypeError("unsupported dtype %s" % a.dtype)
+    es = a.itemsize
+    st = [s // es for s in a.strides]
+    if any(s * es != t for s, t in zip(st, a.strides)) or (a.shape[3] > 1 and st[3] != 1):
+        raise ValueError("feature axis must be contiguous")
+    return _Tensor(a.ctypes.data, _DTYPES[a.dtype], st[0], st[1], st[2])
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def phi(x: float) -> float:
+    return _load().oracle_phi(float(x))
+
+
+def dphi(x: float) -> float:
+    return _load().oracle_dphi(float(x))
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def summary(k: np.ndarray, v: np.ndarray):
+    """S [B,H,d,d] and z [B,H,d] in FP64."""
+    B, H, N, d = k.shape
+    assert v.shape == k.shape
+    S = np.empty((B, H, d, d), np.float64)
+    z = np.empty((B, H, d), np.float64)
+    rc = _load().oracle_summary(B, H, N, d, _tensor(k), _tensor(v), _dptr(S), _dptr(z))
+    if rc:
+        raise ValueError("oracle_summary rejected its arguments")
+    return S, z
+
+
+def apply(q: np.ndarray, S: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """O [B,H,N,d] from queries and a given summary."""
+    B, H, N, d = q.shape
+    S = np.ascontiguousarray(S, np.float64)
+    z = np.ascontiguousarray(z, np.float64)
+    assert S.shape == (B, H, d, d) and z.shape == (B, H, d)
+    o = np.empty((B, H, N, d), np.float64)
+    rc = _load().oracle_apply(B, H, N, d, _tensor(q), _dptr(S), _dptr(z), _dptr(o))
+    if rc:
+        raise ValueError("oracle_apply rejected its arguments")
+    return o
+
+
+def forward(q: np.ndarray, k: np.ndarray, v: np.ndarray, want_summary=False):
+    B, H, N, d = q.shape
+    assert k.shape == q.shape and v.shape == q.shape
+    o = np.empty((B, H, N, d), np.float64)
+    S = np.empty((B, H, d, d), np.float64)
+    z = np.empty((B, H, d), np.float64)
+    rc = _load().oracle_forward(B, H, N, d, _tensor(q), _tensor(k), _tensor(v),
+                                _dptr(o), _dptr(S), _dptr(z))
+    if rc:
+        raise ValueError("oracle_forward rejected its arguments")
+    return (o, S, z) if want_summary else o
+
+
+def backward(q, k, v, g, want_summary=False):
+    """dQ, dK, dV (FP64) of L = <O, G>; optionally dS and dz too."""
+    B, H, N, d = q.shape
+    for a in (k, v, g):
+        assert a.shape == q.shape
+    dq = np.empty((B, H, N, d), np.float64)
+    dk = np.empty_like(dq)
+    dv = np.empty_like(dq)
+    dS = np.empty((B, H, d, d), np.float64)
+    dz = np.empty((B, H, d), np.float64)
+    rc = _load().oracle_backward(B, H, N, d, _tensor(q), _tensor(k), _tensor(v),
+                                 _tensor(g), _dptr(dq), _dptr(dk), _dptr(dv),
+                                 _dptr(dS), _dptr(dz))
+    if rc:
+        raise ValueError("oracle_backward rejected its arguments")
+    return (dq, dk, dv, dS, dz) if want_summary else (dq, dk, dv)

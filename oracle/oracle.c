@@ -1,0 +1,265 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of kernelised linear global attention.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written for a reader to check
+ * against the definition by eye: every token sum is a plain loop in
+ * increasing token order, in FP64.  Parallel loops only split work whose
+ * results are independent (different heads, rows of S, tokens), so the
+ * order of every individual sum is fixed.
+ *
+ * Definition followed (per batch b, head h):
+ *   phi(x) = x + 1 (x > 0), exp(x) (x <= 0); phi'(x) = 1 (x > 0), exp(x).
+ *   S = sum_j phi(k_j) v_j^T,  z = sum_j phi(k_j)
+ *   den_i = phi(q_i) . z,  num_i = S^T phi(q_i),  O_i = num_i / den_i
+ * Backward of L = sum_i G_i . O_i:
+ *   dnum_i = G_i / den_i,  dden_i = -(G_i . O_i) / den_i
+ *   dS = sum_i phi(q_i) dnum_i^T,  dz = sum_i dden_i phi(q_i)
+ *   dQ_i = (S dnum_i + dden_i z) * phi'(q_i)
+ *   dV_j = dS^T phi(k_j),  dK_j = (dS v_j + dz) * phi'(k_j)
+ * The attention is global and non-causal: every query sees every key, as
+ * the paper's spatial self-attention over all tokens of a frame sequence
+ * requires (Sec. III-B).
+ *
+ * parity unpinned: the paper prints no value of this computation; the pins
+ * are mathematical (brute-force quadratic form, closed forms, invariants,
+ * finite differences), kept in the tests.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Exact upcast of one stored element to FP64. */
+static double elem(const oracle_tensor* t, int64_t b, int64_t h, int64_t n,
+                   int64_t c) {
+  int64_t idx = b * t->sb + h * t->sh + n * t->sn + c;
+  if (t->dtype == ORACLE_BF16) {
+    uint32_t u = (uint32_t)((const uint16_t*)t->ptr)[idx] << 16;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+  }
+  if (t->dtype == ORACLE_FP32) return (double)((const float*)t->ptr)[idx];
+  return ((const double*)t->ptr)[idx];
+}
+
+double oracle_phi(double x) { return x > 0.0 ? x + 1.0 : exp(x); }
+double oracle_dphi(double x) { return x > 0.0 ? 1.0 : exp(x); }
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+static int bad_args(int64_t B, int64_t H, int64_t N, int64_t d) {
+  return B < 1 || H < 1 || N < 1 || d < 1;
+}
+
+/* Rows of S handled by one parallel task: a task owns rows [c0, c1) of one
+ * head and walks all N keys in order, so each S[c][e] is one ordered sum. */
+#define ROWS_PER_TASK 16
+
+int oracle_summary(int64_t B, int64_t H, int64_t N, int64_t d,
+                   oracle_tensor k, oracle_tensor v, double* S, double* z) {
+  if (bad_args(B, H, N, d) || !S || !z) return -1;
+  const int64_t nblk = (d + ROWS_PER_TASK - 1) / ROWS_PER_TASK;
+  const int64_t ntask = B * H * nblk;
+#pragma omp parallel
+  {
+    double* vrow = (double*)malloc(sizeof(double) * (size_t)d);
+    double* phik = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t task = 0; task < ntask; ++task) {
+      const int64_t bh = task / nblk, blk = task % nblk;
+      const int64_t b = bh / H, h = bh % H;
+      const int64_t c0 = blk * ROWS_PER_TASK;
+      const int64_t c1 = c0 + ROWS_PER_TASK < d ? c0 + ROWS_PER_TASK : d;
+      double* Sh = S + bh * d * d;
+      double* zh = z + bh * d;
+      for (int64_t c = c0; c < c1; ++c) {
+        zh[c] = 0.0;
+        for (int64_t e = 0; e < d; ++e) Sh[c * d + e] = 0.0;
+      }
+      for (int64_t j = 0; j < N; ++j) {
+        for (int64_t e = 0; e < d; ++e) vrow[e] = elem(&v, b, h, j, e);
+        for (int64_t c = c0; c < c1; ++c) phik[c] = oracle_phi(elem(&k, b, h, j, c));
+        for (int64_t c = c0; c < c1; ++c) {
+          const double p = phik[c];
+          double* Srow = Sh + c * d;
+          for (int64_t e = 0; e < d; ++e) Srow[e] += p * vrow[e];
+          zh[c] += p;
+        }
+      }
+    }
+    free(vrow);
+    free(phik);
+  }
+  return 0;
+}
+
+int oracle_apply(int64_t B, int64_t H, int64_t N, int64_t d,
+                 oracle_tensor q, const double* S, const double* z, double* o) {
+  if (bad_args(B, H, N, d) || !S || !z || !o) return -1;
+  const int64_t rows = B * H * N;
+#pragma omp parallel
+  {
+    double* phiq = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+      const int64_t bh = r / N, i = r % N;
+      const int64_t b = bh / H, h = bh % H;
+      const double* Sh = S + bh * d * d;
+      const double* zh = z + bh * d;
+      double* orow = o + r * d;
+      double den = 0.0;
+      for (int64_t c = 0; c < d; ++c) {
+        phiq[c] = oracle_phi(elem(&q, b, h, i, c));
+        den += phiq[c] * zh[c];
+      }
+      for (int64_t e = 0; e < d; ++e) {
+        double num = 0.0;
+        for (int64_t c = 0; c < d; ++c) num += phiq[c] * Sh[c * d + e];
+        orow[e] = num / den;
+      }
+    }
+    free(phiq);
+  }
+  return 0;
+}
+
+int oracle_forward(int64_t B, int64_t H, int64_t N, int64_t d,
+                   oracle_tensor q, oracle_tensor k, oracle_tensor v,
+                   double* o, double* S, double* z) {
+  if (bad_args(B, H, N, d) || !o) return -1;
+  double* Sb = S ? S : (double*)malloc(sizeof(double) * (size_t)(B * H * d * d));
+  double* zb = z ? z : (double*)malloc(sizeof(double) * (size_t)(B * H * d));
+  int rc = oracle_summary(B, H, N, d, k, v, Sb, zb);
+  if (rc == 0) rc = oracle_apply(B, H, N, d, q, Sb, zb, o);
+  if (!S) free(Sb);
+  if (!z) free(zb);
+  return rc;
+}
+
+/* One head of the backward.  Heads run one after another; the loops inside
+ * split independent tokens or rows across threads. */
+static void backward_head(int64_t b, int64_t h, int64_t N, int64_t d,
+                          const oracle_tensor* q, const oracle_tensor* k,
+                          const oracle_tensor* v, const oracle_tensor* g,
+                          const double* S, const double* z, double* dS,
+                          double* dz, double* dq, double* dk, double* dv) {
+  /* Per query: dnum_i (d values) and dden_i, kept for the dS/dz sums. */
+  double* dnum = (double*)malloc(sizeof(double) * (size_t)(N * d));
+  double* dden = (double*)malloc(sizeof(double) * (size_t)N);
+
+#pragma omp parallel
+  {
+    double* phiq = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      double den = 0.0;
+      for (int64_t c = 0; c < d; ++c) {
+        phiq[c] = oracle_phi(elem(q, b, h, i, c));
+        den += phiq[c] * z[c];
+      }
+      double go = 0.0; /* G_i . O_i */
+      for (int64_t e = 0; e < d; ++e) {
+        double num = 0.0;
+        for (int64_t c = 0; c < d; ++c) num += phiq[c] * S[c * d + e];
+        const double gie = elem(g, b, h, i, e);
+        go += gie * (num / den);
+        dnum[i * d + e] = gie / den;
+      }
+      dden[i] = -go / den;
+    }
+    free(phiq);
+  }
+
+  /* dS and dz: one ordered sum over queries per entry; rows split. */
+  const int64_t nblk = (d + ROWS_PER_TASK - 1) / ROWS_PER_TASK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int64_t c0 = blk * ROWS_PER_TASK;
+    const int64_t c1 = c0 + ROWS_PER_TASK < d ? c0 + ROWS_PER_TASK : d;
+    for (int64_t c = c0; c < c1; ++c) {
+      dz[c] = 0.0;
+      for (int64_t e = 0; e < d; ++e) dS[c * d + e] = 0.0;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      for (int64_t c = c0; c < c1; ++c) {
+        const double p = oracle_phi(elem(q, b, h, i, c));
+        for (int64_t e = 0; e < d; ++e) dS[c * d + e] += p * dnum[i * d + e];
+        dz[c] += dden[i] * p;
+      }
+    }
+  }
+
+  /* dQ_i = (S dnum_i + dden_i z) * phi'(q_i). */
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    for (int64_t c = 0; c < d; ++c) {
+      double acc = 0.0;
+      for (int64_t e = 0; e < d; ++e) acc += S[c * d + e] * dnum[i * d + e];
+      acc += dden[i] * z[c];
+      dq[i * d + c] = acc * oracle_dphi(elem(q, b, h, i, c));
+    }
+  }
+
+  /* dV_j = dS^T phi(k_j);  dK_j = (dS v_j + dz) * phi'(k_j). */
+#pragma omp parallel
+  {
+    double* phik = (double*)malloc(sizeof(double) * (size_t)d);
+    double* vrow = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+      for (int64_t c = 0; c < d; ++c) phik[c] = oracle_phi(elem(k, b, h, j, c));
+      for (int64_t e = 0; e < d; ++e) vrow[e] = elem(v, b, h, j, e);
+      for (int64_t e = 0; e < d; ++e) {
+        double acc = 0.0;
+        for (int64_t c = 0; c < d; ++c) acc += phik[c] * dS[c * d + e];
+        dv[j * d + e] = acc;
+      }
+      for (int64_t c = 0; c < d; ++c) {
+        double acc = 0.0;
+        for (int64_t e = 0; e < d; ++e) acc += dS[c * d + e] * vrow[e];
+        acc += dz[c];
+        dk[j * d + c] = acc * oracle_dphi(elem(k, b, h, j, c));
+      }
+    }
+    free(phik);
+    free(vrow);
+  }
+  free(dnum);
+  free(dden);
+}
+
+int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
+                    oracle_tensor q, oracle_tensor k, oracle_tensor v,
+                    oracle_tensor g, double* dq, double* dk, double* dv,
+                    double* dS, double* dz) {
+  if (bad_args(B, H, N, d) || !dq || !dk || !dv) return -1;
+  double* S = (double*)malloc(sizeof(double) * (size_t)(B * H * d * d));
+  double* z = (double*)malloc(sizeof(double) * (size_t)(B * H * d));
+  double* dSb = dS ? dS : (double*)malloc(sizeof(double) * (size_t)(B * H * d * d));
+  double* dzb = dz ? dz : (double*)malloc(sizeof(double) * (size_t)(B * H * d));
+  int rc = oracle_summary(B, H, N, d, k, v, S, z);
+  if (rc == 0) {
+    for (int64_t bh = 0; bh < B * H; ++bh) {
+      const int64_t b = bh / H, h = bh % H;
+      backward_head(b, h, N, d, &q, &k, &v, &g, S + bh * d * d, z + bh * d,
+                    dSb + bh * d * d, dzb + bh * d, dq + bh * N * d,
+                    dk + bh * N * d, dv + bh * N * d);
+    }
+  }
+  free(S);
+  free(z);
+  if (!dS) free(dSb);
+  if (!dz) free(dzb);
+  return rc;
+}

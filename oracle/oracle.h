@@ -1,0 +1,81 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of kernelised linear global attention.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this code; only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code with the HIP library.
+ *
+ * What it computes (per batch b and head h, with phi applied elementwise):
+ *   phi(x)  = x + 1     for x > 0
+ *           = exp(x)    for x <= 0         (elu(x) + 1)
+ *   S       = sum_j phi(k_j) v_j^T          (d x d summary)
+ *   z       = sum_j phi(k_j)                (normaliser, d-vector)
+ *   O_i     = phi(q_i)^T S / (phi(q_i) . z)
+ * and the exact gradients of L = <O, G> with respect to Q, K, V.
+ *
+ * The paper places a global, non-causal attention over the K x N
+ * spatiotemporal tokens at every denoiser layer (Sec. III-B, spatial
+ * self-attention and temporal cross-attention), and says that its
+ * global attention must be linear in the token count (Sec. III-C).  It
+ * prints no feature map; elu+1 is the reading adopted here (Katharopoulos
+ * et al., 2020), which keeps the summary exactly d x d and the normaliser
+ * strictly positive.
+ *
+ * Inputs are read exactly as the GPU sees them: bfloat16 bit patterns
+ * (uint16), float32 or float64, upcast to FP64 without rounding.  Every
+ * floating-point operation below is FP64.  All sums over tokens run in
+ * increasing token order, so results do not depend on the thread count.
+ *
+ * Tensor addressing: element (b, h, n, c) of an input lives at
+ *   base[b*sb + h*sh + n*sn + c]                       (element strides)
+ * Outputs are dense FP64: O/dQ/dK/dV as [B][H][N][d], S as [B][H][d][d]
+ * (row = key feature c, column = value feature e), z as [B][H][d].
+ */
+#ifndef LA_ORACLE_H
+#define LA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORACLE_BF16 = 0, ORACLE_FP32 = 1, ORACLE_FP64 = 2 };
+
+typedef struct {
+  const void* ptr;
+  int32_t dtype;       /* ORACLE_BF16 / ORACLE_FP32 / ORACLE_FP64 */
+  int64_t sb, sh, sn;  /* element strides; the feature stride is 1 */
+} oracle_tensor;
+
+/* Feature map and its derivative. */
+double oracle_phi(double x);
+double oracle_dphi(double x);
+
+/* S and z per (b, h).  Returns 0, or -1 on a bad argument. */
+int oracle_summary(int64_t B, int64_t H, int64_t N, int64_t d,
+                   oracle_tensor k, oracle_tensor v, double* S, double* z);
+
+/* O from Q and a given (S, z) per (b, h). */
+int oracle_apply(int64_t B, int64_t H, int64_t N, int64_t d,
+                 oracle_tensor q, const double* S, const double* z, double* o);
+
+/* summary followed by apply; S and z may be NULL when not wanted. */
+int oracle_forward(int64_t B, int64_t H, int64_t N, int64_t d,
+                   oracle_tensor q, oracle_tensor k, oracle_tensor v,
+                   double* o, double* S, double* z);
+
+/* Gradients of L = <O, G>.  dq, dk, dv are dense [B][H][N][d]; dS and dz
+ * ([B][H][d][d], [B][H][d]) may be NULL. */
+int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
+                    oracle_tensor q, oracle_tensor k, oracle_tensor v,
+                    oracle_tensor g, double* dq, double* dk, double* dv,
+                    double* dS, double* dz);
+
+/* Number of OpenMP threads the oracle will use. */
+int oracle_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,266 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle (oracle/oracle.c) against an independent fact:
+a hand-derived example, the brute-force quadratic form written here in
+numpy, closed forms for degenerate inputs, invariances of the definition,
+finite differences, and autograd of the quadratic form.  None of them
+re-types the oracle's own loops.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_16590_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def phi_np(x):
+    return np.where(x > 0, x + 1.0, np.exp(np.minimum(x, 0.0)))
+
+
+def quadratic_form(q, k, v):
+    """(phi(Q) phi(K)^T) V with each row divided by its row sum."""
+    A = np.einsum("bhic,bhjc->bhij", phi_np(q), phi_np(k))
+    return np.einsum("bhij,bhje->bhie", A, v) / A.sum(-1, keepdims=True)
+
+
+def normwise(a, ref):
+    return np.linalg.norm((a - ref).ravel()) / np.linalg.norm(ref.ravel())
+
+
+def rnd(shape, seed, scale=1.0):
+    return scale * np.random.default_rng(seed).standard_normal(shape)
+
+
+# -- golden worked example ---------------------------------------------------
+
+def _read_golden(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows.setdefault(key, []).append([_frac(x) for x in vals])
+    return rows
+
+
+def _frac(s):
+    # sums of rationals such as "-5/32+64/243"
+    total = Fraction(0)
+    for term in s.replace("-", "+-").split("+"):
+        if term:
+            total += Fraction(term)
+    return total
+
+
+def test_golden_tiny_example():
+    g = _read_golden("tiny_d2_n2.txt")
+    arr = lambda key: np.array([[float(x) for x in r] for r in g[key]])[None, None]
+    q, k, v, G = arr("q"), arr("k"), arr("v"), arr("g")
+    o, S, z = oracle.forward(q, k, v, want_summary=True)
+    np.testing.assert_allclose(o, arr("o"), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(S[0, 0], arr("S")[0, 0], rtol=0, atol=0)
+    np.testing.assert_allclose(z[0, 0], arr("z")[0, 0, 0], rtol=0, atol=0)
+    dq, dk, dv, dS, dz = oracle.backward(q, k, v, G, want_summary=True)
+    np.testing.assert_allclose(dq, arr("dq"), rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(dk, arr("dk"), rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(dv, arr("dv"), rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(dS[0, 0], arr("dS")[0, 0], rtol=1e-15)
+    np.testing.assert_allclose(dz[0, 0], arr("dz")[0, 0, 0], rtol=1e-15)
+
+
+# -- feature map -------------------------------------------------------------
+
+def test_phi_branches_and_continuity():
+    assert oracle.phi(0.0) == 1.0
+    assert oracle.phi(1.0) == 2.0
+    assert oracle.phi(-1.0) == math.exp(-1.0)
+    assert oracle.phi(2.5) == 3.5
+    assert abs(oracle.phi(1e-12) - oracle.phi(-1e-12)) < 3e-12
+    assert oracle.dphi(0.5) == 1.0
+    assert oracle.dphi(-2.0) == math.exp(-2.0)
+    assert oracle.dphi(0.0) == 1.0
+    assert oracle.phi(-800.0) == 0.0  # underflow stays non-negative
+
+
+# -- forward -----------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [1, 4, 16, 64])
+@pytest.mark.parametrize("N", [1, 7, 300])
+def test_forward_matches_quadratic_form(N, d):
+    q, k, v = (rnd((2, 3, N, d), s) for s in (1, 2, 3))
+    o = oracle.forward(q, k, v)
+    ref = quadratic_form(q, k, v)
+    assert normwise(o, ref) < 1e-13
+    assert np.abs(o - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_forward_quadratic_form_long():
+    q, k, v = (rnd((1, 1, 2048, 16), s, 1.5) for s in (4, 5, 6))
+    assert normwise(oracle.forward(q, k, v), quadratic_form(q, k, v)) < 1e-12
+
+
+def test_summary_is_phi_k_transpose_v():
+    k, v = rnd((2, 2, 129, 8), 7), rnd((2, 2, 129, 8), 8)
+    S, z = oracle.summary(k, v)
+    np.testing.assert_allclose(S, np.einsum("bhjc,bhje->bhce", phi_np(k), v), rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(z, phi_np(k).sum(2), rtol=1e-14)
+
+
+def test_constant_values_give_that_value():
+    q, k = rnd((1, 2, 500, 16), 9, 2.0), rnd((1, 2, 500, 16), 10, 2.0)
+    row = rnd((1, 2, 1, 16), 11)
+    v = np.broadcast_to(row, q.shape).copy()
+    o = oracle.forward(q, k, v)
+    assert np.abs(o - row).max() <= 1e-14 * np.abs(row).max() * 4
+
+
+def test_constant_keys_give_mean_of_values():
+    q, v = rnd((1, 1, 257, 8), 12), rnd((1, 1, 257, 8), 13)
+    k = np.broadcast_to(rnd((1, 1, 1, 8), 14), q.shape).copy()
+    o = oracle.forward(q, k, v)
+    np.testing.assert_allclose(o, np.broadcast_to(v.mean(2, keepdims=True), o.shape), rtol=0, atol=1e-13)
+
+
+def test_single_token_returns_its_value():
+    q, k, v = (rnd((3, 2, 1, 32), s) for s in (15, 16, 17))
+    np.testing.assert_allclose(oracle.forward(q, k, v), v, rtol=1e-15, atol=0)
+
+
+def test_scalar_head_is_independent_of_query():
+    q, k, v = (rnd((1, 1, 64, 1), s) for s in (18, 19, 20))
+    pk = phi_np(k)
+    expect = (pk * v).sum() / pk.sum()
+    np.testing.assert_allclose(oracle.forward(q, k, v), expect, rtol=1e-14)
+
+
+def test_outputs_lie_in_convex_hull_of_values():
+    q, k, v = (rnd((2, 2, 400, 16), s, 2.0) for s in (21, 22, 23))
+    o = oracle.forward(q, k, v)
+    lo, hi = v.min(2, keepdims=True), v.max(2, keepdims=True)
+    assert np.all(o >= lo - 1e-14) and np.all(o <= hi + 1e-14)
+
+
+def test_key_permutation_invariance_and_query_equivariance():
+    q, k, v = (rnd((1, 2, 333, 16), s) for s in (24, 25, 26))
+    o = oracle.forward(q, k, v)
+    pk = np.random.default_rng(27).permutation(333)
+    pq = np.random.default_rng(28).permutation(333)
+    o2 = oracle.forward(q[:, :, pq], k[:, :, pk], v[:, :, pk])
+    assert np.abs(o2 - o[:, :, pq]).max() < 1e-13
+
+
+def test_heads_and_batches_are_independent():
+    q, k, v = (rnd((2, 3, 100, 8), s) for s in (29, 30, 31))
+    o = oracle.forward(q, k, v)
+    o12 = oracle.forward(q[1:2, 2:3], k[1:2, 2:3], v[1:2, 2:3])
+    np.testing.assert_array_equal(o[1:2, 2:3], o12)
+
+
+def test_affine_equivariance_in_values():
+    q, k, v = (rnd((1, 1, 200, 16), s) for s in (32, 33, 34))
+    a, c = -1.75, rnd((1, 1, 1, 16), 35)
+    o = oracle.forward(q, k, v)
+    o2 = oracle.forward(q, k, a * v + c)
+    assert np.abs(o2 - (a * o + c)).max() < 1e-13
+
+
+def test_bf16_and_fp32_inputs_are_upcast_exactly():
+    f = inputs.generate(inputs.GenSpec(seed=5, stream=0), (1, 2, 64, 16), "fp32")
+    bits = inputs.generate(inputs.GenSpec(seed=5, stream=1), (1, 2, 64, 16), "bf16")
+    kb = inputs.generate(inputs.GenSpec(seed=5, stream=2), (1, 2, 64, 16), "bf16")
+    o_mixed = oracle.forward(f, bits, kb)
+    o_64 = oracle.forward(f.astype(np.float64), inputs.as_float64(bits), inputs.as_float64(kb))
+    np.testing.assert_array_equal(o_mixed, o_64)
+
+
+def test_strided_inputs_match_contiguous():
+    # BNHD storage viewed as BHND, as a fused projection would hand it over
+    base = rnd((2, 50, 3, 16), 36)
+    q = base.transpose(0, 2, 1, 3)
+    k = rnd((2, 50, 3, 16), 37).transpose(0, 2, 1, 3)
+    v = rnd((2, 50, 3, 16), 38).transpose(0, 2, 1, 3)
+    o = oracle.forward(q, k, v)
+    o_c = oracle.forward(*(np.ascontiguousarray(x) for x in (q, k, v)))
+    np.testing.assert_array_equal(o, o_c)
+
+
+def test_apply_with_given_summary_matches_forward():
+    q, k, v = (rnd((1, 2, 90, 8), s) for s in (39, 40, 41))
+    o, S, z = oracle.forward(q, k, v, want_summary=True)
+    np.testing.assert_array_equal(oracle.apply(q, S, z), o)
+
+
+def test_summary_of_split_keys_adds_up():
+    # S and z are sums over tokens: shards of the key range add to the whole
+    k, v = rnd((1, 2, 300, 8), 42), rnd((1, 2, 300, 8), 43)
+    S, z = oracle.summary(k, v)
+    S1, z1 = oracle.summary(k[:, :, :123], v[:, :, :123])
+    S2, z2 = oracle.summary(k[:, :, 123:], v[:, :, 123:])
+    np.testing.assert_allclose(S1 + S2, S, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(z1 + z2, z, rtol=1e-14)
+
+
+# -- backward ----------------------------------------------------------------
+
+def _loss(q, k, v, g):
+    return float((oracle.forward(q, k, v) * g).sum())
+
+
+def test_backward_matches_central_differences_all_coordinates():
+    N, d = 512, 16
+    q, k, v, g = (rnd((1, 1, N, d), s) for s in (44, 45, 46, 47))
+    dq, dk, dv = oracle.backward(q, k, v, g)
+    rng = np.random.default_rng(48)
+    # every coordinate of every input, central differences on the oracle
+    for name, x, grad in (("q", q, dq), ("k", k, dk), ("v", v, dv)):
+        fd = np.empty_like(x)
+        flat = x.reshape(-1)
+        for idx in range(flat.size):
+            x0 = flat[idx]
+            h = 1e-6 * max(1.0, abs(x0))
+            flat[idx] = x0 + h
+            lp = _loss(q, k, v, g)
+            flat[idx] = x0 - h
+            lm = _loss(q, k, v, g)
+            flat[idx] = x0
+            fd.reshape(-1)[idx] = (lp - lm) / (2 * h)
+        err = normwise(grad, fd)
+        assert err < 1e-6, (name, err)
+    del rng
+
+
+def test_backward_matches_autograd_of_quadratic_form():
+    torch = pytest.importorskip("torch")
+    q, k, v, g = (rnd((2, 2, 200, 8), s) for s in (49, 50, 51, 52))
+    tq, tk, tv = (torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in (q, k, v))
+
+    def phi_t(x):
+        return torch.where(x > 0, x + 1, torch.exp(torch.clamp(x, max=0)))
+
+    A = phi_t(tq) @ phi_t(tk).transpose(-1, -2)
+    o = (A @ tv) / A.sum(-1, keepdim=True)
+    (o * torch.tensor(g)).sum().backward()
+    dq, dk, dv = oracle.backward(q, k, v, g)
+    for ours, ref in ((dq, tq.grad), (dk, tk.grad), (dv, tv.grad)):
+        assert normwise(ours, ref.numpy()) < 1e-12
+
+
+def test_value_gradient_column_sums_equal_upstream_sums():
+    q, k, v, g = (rnd((1, 2, 1000, 16), s) for s in (53, 54, 55, 56))
+    _, _, dv = oracle.backward(q, k, v, g)
+    np.testing.assert_allclose(dv.sum(2), g.sum(2), rtol=1e-11, atol=1e-11)
+
+
+def test_constant_values_have_zero_query_and_key_gradients():
+    q, k, g = (rnd((1, 1, 300, 16), s) for s in (57, 58, 59))
+    v = np.broadcast_to(rnd((1, 1, 1, 16), 60), q.shape).copy()
+    dq, dk, _ = oracle.backward(q, k, v, g)
+    assert np.abs(dq).max() < 1e-14 and np.abs(dk).max() < 1e-14

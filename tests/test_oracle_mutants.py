@@ -1,0 +1,101 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies oracle/oracle.c, plants one mistake (a transposed operand,
+a dropped term, a wrong sign, an off-by-one), builds the copy on the CPU and
+runs a compact set of the same pins as test_oracle.py against it.  Every
+mutant must fail at least one pin, and the unmodified source must pass all
+of them.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "apply_transposed_S": ("num += phiq[c] * Sh[c * d + e];", "num += phiq[c] * Sh[e * d + c];"),
+    "apply_no_division": ("orow[e] = num / den;", "orow[e] = num;"),
+    "summary_z_counts_tokens": ("zh[c] += p;", "zh[c] += 1.0;"),
+    "summary_skips_first_key": ("for (int64_t j = 0; j < N; ++j) {\n        for (int64_t e = 0; e < d; ++e) vrow[e] = elem(&v",
+                                "for (int64_t j = 1; j < N; ++j) {\n        for (int64_t e = 0; e < d; ++e) vrow[e] = elem(&v"),
+    "phi_drops_one": ("return x > 0.0 ? x + 1.0 : exp(x); }", "return x > 0.0 ? x : exp(x); }"),
+    "phi_negated_exponent": ("return x > 0.0 ? x + 1.0 : exp(x); }", "return x > 0.0 ? x + 1.0 : exp(-x); }"),
+    "dphi_zero_slope": ("return x > 0.0 ? 1.0 : exp(x); }", "return x > 0.0 ? 0.0 : exp(x); }"),
+    "dden_sign": ("dden[i] = -go / den;", "dden[i] = go / den;"),
+    "dq_drops_z_term": ("acc += dden[i] * z[c];", ""),
+    "dk_drops_dz_term": ("acc += dz[c];", ""),
+    "dv_transposed_dS": ("acc += phik[c] * dS[c * d + e];", "acc += phik[c] * dS[e * d + c];"),
+    "dq_uses_phi_not_dphi": ("dq[i * d + c] = acc * oracle_dphi(", "dq[i * d + c] = acc * oracle_phi("),
+    "dS_uses_raw_gradient": ("dS[c * d + e] += p * dnum[i * d + e];",
+                             "dS[c * d + e] += p * elem(g, b, h, i, e);"),
+}
+
+
+def phi_np(x):
+    return np.where(x > 0, x + 1.0, np.exp(np.minimum(x, 0.0)))
+
+
+def _pins():
+    """Return the names of the pins that fail for the loaded oracle."""
+    failed = []
+    rng = np.random.default_rng(7)
+    q, k, v, g = (rng.standard_normal((1, 2, 40, 4)) for _ in range(4))
+    A = np.einsum("bhic,bhjc->bhij", phi_np(q), phi_np(k))
+    ref = np.einsum("bhij,bhje->bhie", A, v) / A.sum(-1, keepdims=True)
+    o = oracle.forward(q, k, v)
+    if not np.allclose(o, ref, rtol=1e-12, atol=1e-12):
+        failed.append("quadratic_form")
+    dq, dk, dv = oracle.backward(q, k, v, g)
+    for name, x, grad in (("q", q, dq), ("k", k, dk), ("v", v, dv)):
+        fd = np.empty_like(x)
+        for idx in np.ndindex(x.shape):
+            x0 = x[idx]
+            h = 1e-6 * max(1.0, abs(x0))
+            x[idx] = x0 + h
+            lp = (oracle.forward(q, k, v) * g).sum()
+            x[idx] = x0 - h
+            lm = (oracle.forward(q, k, v) * g).sum()
+            x[idx] = x0
+            fd[idx] = (lp - lm) / (2 * h)
+        if not np.allclose(grad, fd, rtol=1e-5, atol=1e-7):
+            failed.append("fd_" + name)
+    if not np.allclose(dv.sum(2), g.sum(2), rtol=1e-11, atol=1e-11):
+        failed.append("dv_column_sums")
+    return failed
+
+
+def _build(tmp_path, text, name):
+    src = tmp_path / (name + ".c")
+    src.write_text(text)
+    so = tmp_path / ("lib" + name + ".so")
+    inc = os.path.dirname(SRC)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-I", inc,
+                    "-o", str(so), str(src), "-lm"], check=True)
+    return str(so)
+
+
+def _with_library(path):
+    prev = oracle.use_library(path)
+    try:
+        return _pins()
+    finally:
+        oracle.restore_library(prev)
+
+
+def test_unmodified_oracle_passes_compact_pins(tmp_path):
+    so = _build(tmp_path, open(SRC).read(), "pristine")
+    assert _with_library(so) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not unique: " + name
+    so = _build(tmp_path, text.replace(old, new), name)
+    failed = _with_library(so)
+    assert failed, "no pin caught the planted mistake " + name
