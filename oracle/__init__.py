@@ -75,6 +75,8 @@ def _load(path=None):
         lib.oracle_forward.argtypes = [i64, i64, i64, i64, T, T, T, dp, dp, dp]
         lib.oracle_backward.argtypes = [i64, i64, i64, i64, T, T, T, T,
                                         dp, dp, dp, dp, dp]
+        lib.oracle_backward_query.argtypes = [i64, i64, i64, i64, T, T, dp, dp, dp, dp, dp]
+        lib.oracle_backward_key.argtypes = [i64, i64, i64, i64, T, T, dp, dp, dp, dp]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -166,3 +168,34 @@ def backward(q, k, v, g, want_summary=False):
     if rc:
         raise ValueError("oracle_backward rejected its arguments")
     return (dq, dk, dv, dS, dz) if want_summary else (dq, dk, dv)
+
+
+def backward_query(q, g, S, z, want_dq=True):
+    """dQ (or None), dS, dz for the given queries against a given (S, z)."""
+    B, H, N, d = q.shape
+    assert g.shape == q.shape
+    S = np.ascontiguousarray(S, np.float64)
+    z = np.ascontiguousarray(z, np.float64)
+    dq = np.empty((B, H, N, d), np.float64) if want_dq else None
+    dS = np.empty((B, H, d, d), np.float64)
+    dz = np.empty((B, H, d), np.float64)
+    rc = _load().oracle_backward_query(B, H, N, d, _tensor(q), _tensor(g), _dptr(S), _dptr(z),
+                                       _dptr(dq) if dq is not None else None, _dptr(dS), _dptr(dz))
+    if rc:
+        raise ValueError("oracle_backward_query rejected its arguments")
+    return dq, dS, dz
+
+
+def backward_key(k, v, dS, dz):
+    """dK, dV for the given keys from (dS, dz)."""
+    B, H, N, d = k.shape
+    assert v.shape == k.shape
+    dS = np.ascontiguousarray(dS, np.float64)
+    dz = np.ascontiguousarray(dz, np.float64)
+    dk = np.empty((B, H, N, d), np.float64)
+    dv = np.empty_like(dk)
+    rc = _load().oracle_backward_key(B, H, N, d, _tensor(k), _tensor(v), _dptr(dS), _dptr(dz),
+                                     _dptr(dk), _dptr(dv))
+    if rc:
+        raise ValueError("oracle_backward_key rejected its arguments")
+    return dk, dv

@@ -147,13 +147,12 @@ int oracle_forward(int64_t B, int64_t H, int64_t N, int64_t d,
   return rc;
 }
 
-/* One head of the backward.  Heads run one after another; the loops inside
- * split independent tokens or rows across threads. */
-static void backward_head(int64_t b, int64_t h, int64_t N, int64_t d,
-                          const oracle_tensor* q, const oracle_tensor* k,
-                          const oracle_tensor* v, const oracle_tensor* g,
-                          const double* S, const double* z, double* dS,
-                          double* dz, double* dq, double* dk, double* dv) {
+/* Query side of the backward for one head: dnum_i and dden_i per query,
+ * dS and dz (ordered sums over queries), and dQ.  dq may be NULL. */
+static void backward_query_head(int64_t b, int64_t h, int64_t N, int64_t d,
+                                const oracle_tensor* q, const oracle_tensor* g,
+                                const double* S, const double* z, double* dS,
+                                double* dz, double* dq) {
   /* Per query: dnum_i (d values) and dden_i, kept for the dS/dz sums. */
   double* dnum = (double*)malloc(sizeof(double) * (size_t)(N * d));
   double* dden = (double*)malloc(sizeof(double) * (size_t)N);
@@ -201,16 +200,26 @@ static void backward_head(int64_t b, int64_t h, int64_t N, int64_t d,
   }
 
   /* dQ_i = (S dnum_i + dden_i z) * phi'(q_i). */
+  if (dq) {
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < N; ++i) {
-    for (int64_t c = 0; c < d; ++c) {
-      double acc = 0.0;
-      for (int64_t e = 0; e < d; ++e) acc += S[c * d + e] * dnum[i * d + e];
-      acc += dden[i] * z[c];
-      dq[i * d + c] = acc * oracle_dphi(elem(q, b, h, i, c));
+    for (int64_t i = 0; i < N; ++i) {
+      for (int64_t c = 0; c < d; ++c) {
+        double acc = 0.0;
+        for (int64_t e = 0; e < d; ++e) acc += S[c * d + e] * dnum[i * d + e];
+        acc += dden[i] * z[c];
+        dq[i * d + c] = acc * oracle_dphi(elem(q, b, h, i, c));
+      }
     }
   }
+  free(dnum);
+  free(dden);
+}
 
+/* Key side of the backward for one head, given dS and dz. */
+static void backward_key_head(int64_t b, int64_t h, int64_t N, int64_t d,
+                              const oracle_tensor* k, const oracle_tensor* v,
+                              const double* dS, const double* dz, double* dk,
+                              double* dv) {
   /* dV_j = dS^T phi(k_j);  dK_j = (dS v_j + dz) * phi'(k_j). */
 #pragma omp parallel
   {
@@ -235,8 +244,26 @@ static void backward_head(int64_t b, int64_t h, int64_t N, int64_t d,
     free(phik);
     free(vrow);
   }
-  free(dnum);
-  free(dden);
+}
+
+int oracle_backward_query(int64_t B, int64_t H, int64_t N, int64_t d,
+                          oracle_tensor q, oracle_tensor g, const double* S,
+                          const double* z, double* dq, double* dS, double* dz) {
+  if (bad_args(B, H, N, d) || !S || !z || !dS || !dz) return -1;
+  for (int64_t bh = 0; bh < B * H; ++bh)
+    backward_query_head(bh / H, bh % H, N, d, &q, &g, S + bh * d * d, z + bh * d,
+                        dS + bh * d * d, dz + bh * d, dq ? dq + bh * N * d : NULL);
+  return 0;
+}
+
+int oracle_backward_key(int64_t B, int64_t H, int64_t N, int64_t d,
+                        oracle_tensor k, oracle_tensor v, const double* dS,
+                        const double* dz, double* dk, double* dv) {
+  if (bad_args(B, H, N, d) || !dS || !dz || !dk || !dv) return -1;
+  for (int64_t bh = 0; bh < B * H; ++bh)
+    backward_key_head(bh / H, bh % H, N, d, &k, &v, dS + bh * d * d, dz + bh * d,
+                      dk + bh * N * d, dv + bh * N * d);
+  return 0;
 }
 
 int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
@@ -249,14 +276,8 @@ int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
   double* dSb = dS ? dS : (double*)malloc(sizeof(double) * (size_t)(B * H * d * d));
   double* dzb = dz ? dz : (double*)malloc(sizeof(double) * (size_t)(B * H * d));
   int rc = oracle_summary(B, H, N, d, k, v, S, z);
-  if (rc == 0) {
-    for (int64_t bh = 0; bh < B * H; ++bh) {
-      const int64_t b = bh / H, h = bh % H;
-      backward_head(b, h, N, d, &q, &k, &v, &g, S + bh * d * d, z + bh * d,
-                    dSb + bh * d * d, dzb + bh * d, dq + bh * N * d,
-                    dk + bh * N * d, dv + bh * N * d);
-    }
-  }
+  if (rc == 0) rc = oracle_backward_query(B, H, N, d, q, g, S, z, dq, dSb, dzb);
+  if (rc == 0) rc = oracle_backward_key(B, H, N, d, k, v, dSb, dzb, dk, dv);
   free(S);
   free(z);
   if (!dS) free(dSb);

@@ -72,6 +72,18 @@ int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
                     oracle_tensor g, double* dq, double* dk, double* dv,
                     double* dS, double* dz);
 
+/* The two halves of oracle_backward.  Query side: from Q, G and the
+ * forward's S, z, the sums dS, dz over the given queries and (dq non-NULL)
+ * dQ of those queries.  Key side: dK, dV of the given keys from dS, dz.
+ * dQ rows depend only on (S, z, q_i, g_i) and dK/dV rows only on
+ * (dS, dz, k_j, v_j), so both may be evaluated on a subset of rows. */
+int oracle_backward_query(int64_t B, int64_t H, int64_t N, int64_t d,
+                          oracle_tensor q, oracle_tensor g, const double* S,
+                          const double* z, double* dq, double* dS, double* dz);
+int oracle_backward_key(int64_t B, int64_t H, int64_t N, int64_t d,
+                        oracle_tensor k, oracle_tensor v, const double* dS,
+                        const double* dz, double* dk, double* dv);
+
 /* Number of OpenMP threads the oracle will use. */
 int oracle_threads(void);
 

@@ -1,0 +1,226 @@
+"""ctypes binding of liblinattn.so (include/la.h) and liblagen.so.
+
+Argument marshalling only: every step of the attention runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory and the current
+HIP stream.  There is no fallback: if the library is missing or a call
+fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblinattn.so")
+GEN_PATH = os.path.join(_HERE, "liblagen.so")
+
+LA_BF16, LA_FP32 = 0, 1
+LA_PHI_ELU1 = 0
+STATUS = {0: "LA_OK", 1: "LA_ERR_INVALID_ARG", 2: "LA_ERR_UNSUPPORTED", 3: "LA_ERR_OOM",
+          4: "LA_ERR_HIP", 5: "LA_ERR_NOT_FOUND", 6: "LA_ERR_SHUTDOWN", 7: "LA_ERR_BUSY"}
+
+
+class LaError(RuntimeError):
+    def __init__(self, call, status, hip_error=0):
+        self.status = status
+        self.hip_error = hip_error
+        msg = "%s returned %s" % (call, STATUS.get(status, status))
+        if hip_error:
+            msg += " (hipError %d)" % hip_error
+        super().__init__(msg)
+
+
+class AttnDesc(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int64), ("H", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("d", ctypes.c_int64), ("in_dtype", ctypes.c_int32),
+                ("out_dtype", ctypes.c_int32),
+                ("in_sb", ctypes.c_int64), ("in_sh", ctypes.c_int64), ("in_sn", ctypes.c_int64),
+                ("out_sb", ctypes.c_int64), ("out_sh", ctypes.c_int64), ("out_sn", ctypes.c_int64),
+                ("feature_map", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class GenSpec(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32),
+                ("tensor_id", ctypes.c_int32), ("mean", ctypes.c_double),
+                ("std", ctypes.c_double), ("grid_T", ctypes.c_int32),
+                ("grid_lat", ctypes.c_int32), ("grid_lon", ctypes.c_int32),
+                ("amplitude", ctypes.c_double)]
+
+
+_lib = None
+_gen = None
+VP = ctypes.c_void_p
+
+
+def lib():
+    """The attention library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblinattn.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        DP = ctypes.POINTER(AttnDesc)
+        L.la_status_string.restype = ctypes.c_char_p
+        L.la_status_string.argtypes = [ctypes.c_int]
+        L.la_last_hip_error.restype = ctypes.c_int32
+        L.la_version.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 2
+        L.la_workspace_size.argtypes = [DP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.la_forward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
+        L.la_backward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
+        for name in ("la_version", "la_workspace_size", "la_forward", "la_backward"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def gen_lib():
+    global _gen
+    if _gen is None:
+        if not os.path.exists(GEN_PATH):
+            raise RuntimeError("liblagen.so is not built (run __graft_entry__.build())")
+        G = ctypes.CDLL(GEN_PATH)
+        G.la_gen_fill.restype = ctypes.c_int32
+        G.la_gen_fill.argtypes = [VP, ctypes.c_int32] + [ctypes.c_int64] * 7 + [
+            ctypes.POINTER(GenSpec), VP]
+        _gen = G
+    return _gen
+
+
+def _check(call, status):
+    if status != 0:
+        raise LaError(call, status, lib().la_last_hip_error() if status == 4 else 0)
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.bfloat16:
+        return LA_BF16
+    if t == torch.float32:
+        return LA_FP32
+    raise TypeError("unsupported dtype %s (bfloat16 or float32)" % t)
+
+
+def _strides(x: torch.Tensor):
+    if x.dim() != 4:
+        raise ValueError("expected a [B, H, N, d] tensor")
+    if x.shape[3] > 1 and x.stride(3) != 1:
+        raise ValueError("the feature axis must be contiguous")
+    return x.stride(0), x.stride(1), x.stride(2)
+
+
+def make_desc(q: torch.Tensor, out: torch.Tensor) -> AttnDesc:
+    B, H, N, d = q.shape
+    isb, ish, isn = _strides(q)
+    osb, osh, osn = _strides(out)
+    return AttnDesc(B, H, N, d, _dtype_code(q.dtype), _dtype_code(out.dtype),
+                    isb, ish, isn, osb, osh, osn, LA_PHI_ELU1, 0)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_size(desc: AttnDesc, pass_: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check("la_workspace_size", lib().la_workspace_size(ctypes.byref(desc), pass_, ctypes.byref(n)))
+    return n.value
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned well beyond 256 bytes
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _same_layout(ref: torch.Tensor, x: torch.Tensor, name: str):
+    if x.shape != ref.shape or x.dtype != ref.dtype or x.device != ref.device:
+        raise ValueError("%s must match q in shape, dtype and device" % name)
+    if _strides(x) != _strides(ref):
+        raise ValueError("%s must have the same strides as q" % name)
+
+
+def forward(q, k, v, out_dtype=None, return_summary=False, out=None):
+    """O = linear attention of (q, k, v), [B, H, N, d] tensors on the GPU.
+
+    With return_summary=True also returns S [B,H,d,d] and z [B,H,d] (FP64).
+    """
+    _same_layout(q, k, "k")
+    _same_layout(q, v, "v")
+    if not q.is_cuda:
+        raise ValueError("inputs must be GPU tensors")
+    B, H, N, d = q.shape
+    if out is None:
+        out = torch.empty((B, H, N, d), dtype=out_dtype or q.dtype, device=q.device)
+    desc = make_desc(q, out)
+    ws = _workspace(workspace_size(desc, 0), q.device)
+    S = z = None
+    if return_summary:
+        S = torch.empty((B, H, d, d), dtype=torch.float64, device=q.device)
+        z = torch.empty((B, H, d), dtype=torch.float64, device=q.device)
+    _check("la_forward", lib().la_forward(
+        ctypes.byref(desc), q.data_ptr(), k.data_ptr(), v.data_ptr(), out.data_ptr(),
+        S.data_ptr() if S is not None else None, z.data_ptr() if z is not None else None,
+        ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return (out, S, z) if return_summary else out
+
+
+def backward(q, k, v, S, z, dout, grad_dtype=None):
+    """dQ, dK, dV of L = <O, dout> given the forward's S and z."""
+    _same_layout(q, k, "k")
+    _same_layout(q, v, "v")
+    _same_layout(q, dout, "dout")
+    B, H, N, d = q.shape
+    gd = grad_dtype or q.dtype
+    dq = torch.empty((B, H, N, d), dtype=gd, device=q.device)
+    dk = torch.empty_like(dq)
+    dv = torch.empty_like(dq)
+    S = S.contiguous()
+    z = z.contiguous()
+    desc = make_desc(q, dq)
+    ws = _workspace(workspace_size(desc, 1), q.device)
+    _check("la_backward", lib().la_backward(
+        ctypes.byref(desc), q.data_ptr(), k.data_ptr(), v.data_ptr(), S.data_ptr(),
+        z.data_ptr(), dout.data_ptr(), dq.data_ptr(), dk.data_ptr(), dv.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return dq, dk, dv
+
+
+def gen_fill(x: torch.Tensor, seed: int, stream_id: int, mean=0.0, std=1.0, grid=None,
+             amplitude=1.0, tensor_id=None):
+    """Fill a [B,H,N,d] GPU tensor with the seeded synthetic inputs."""
+    B, H, N, d = x.shape
+    sb, sh, sn = _strides(x)
+    T, nlat, nlon = grid if grid else (0, 0, 0)
+    spec = GenSpec(seed, stream_id, stream_id if tensor_id is None else tensor_id,
+                   mean, std, T, nlat, nlon, amplitude)
+    rc = gen_lib().la_gen_fill(x.data_ptr(), _dtype_code(x.dtype), B, H, N, d, sb, sh, sn,
+                               ctypes.byref(spec), _stream(x.device))
+    if rc != 0:
+        raise LaError("la_gen_fill", rc)
+    return x
+
+
+class LinearAttention(torch.autograd.Function):
+    """Linear global attention with the hand-written backward.
+
+    The forward saves q, k, v and the FP64 summary (S, z); phi(Q) and phi(K)
+    are recomputed in the backward, never stored.
+    """
+
+    @staticmethod
+    def forward(ctx, q, k, v):
+        o, S, z = forward(q, k, v, return_summary=True)
+        ctx.save_for_backward(q, k, v, S, z)
+        return o
+
+    @staticmethod
+    def backward(ctx, do):
+        q, k, v, S, z = ctx.saved_tensors
+        if do.dtype != q.dtype or _strides(do) != _strides(q):
+            buf = torch.empty_strided(q.shape, q.stride(), dtype=q.dtype, device=q.device)
+            do = buf.copy_(do)
+        return backward(q, k, v, S, z, do)
+
+
+def linear_attention(q, k, v):
+    return LinearAttention.apply(q, k, v)

@@ -1,0 +1,218 @@
+// la_api.cpp -- the C ABI of liblinattn (include/la.h): argument checks,
+// tiling choices, workspace layout and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/la.h"
+#include "la_kernels.h"
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+la_status hip_fail(hipError_t e) {
+  g_last_hip_error = (int32_t)e;
+  return LA_ERR_HIP;
+}
+
+int elem_size(int32_t dt) { return dt == LA_BF16 ? 2 : 4; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+la_status check_desc(const la_attn_desc* d) {
+  if (!d) return LA_ERR_INVALID_ARG;
+  if (d->B < 1 || d->H < 1 || d->N < 1 || d->d < 1) return LA_ERR_INVALID_ARG;
+  if (d->in_dtype != LA_BF16 && d->in_dtype != LA_FP32) return LA_ERR_INVALID_ARG;
+  if (d->out_dtype != LA_BF16 && d->out_dtype != LA_FP32) return LA_ERR_INVALID_ARG;
+  if (d->feature_map != LA_PHI_ELU1) return LA_ERR_UNSUPPORTED;
+  if (d->flags != 0) return LA_ERR_INVALID_ARG;
+  if (d->d != 16 && d->d != 32 && d->d != 64 && d->d != 128) return LA_ERR_UNSUPPORTED;
+  // the grid's y dimension carries (b, h); the token index is 64-bit
+  if (d->B * d->H > 65535 || d->N > (int64_t(1) << 40)) return LA_ERR_UNSUPPORTED;
+  const int64_t s[2][3] = {{d->in_sb, d->in_sh, d->in_sn}, {d->out_sb, d->out_sh, d->out_sn}};
+  const int es[2] = {elem_size(d->in_dtype), elem_size(d->out_dtype)};
+  for (int t = 0; t < 2; ++t) {
+    for (int i = 0; i < 3; ++i) {
+      if (s[t][i] < 0) return LA_ERR_INVALID_ARG;
+      if ((s[t][i] * es[t]) % 16 != 0) return LA_ERR_INVALID_ARG;
+    }
+    if (s[t][2] < d->d) return LA_ERR_INVALID_ARG;
+  }
+  return LA_OK;
+}
+
+// Tiling.  Depends only on (N, d, dtype) so that the same (b, h) problem
+// gives bitwise the same result whatever batch it is part of.
+struct Tiling {
+  int P;   // partial sums per (b, h)
+  int Tw;  // tokens per partial (a multiple of 32)
+  int Ta;  // tokens per apply workgroup
+};
+
+Tiling choose_tiling(int64_t N, int d) {
+  const int64_t tw_min = d >= 128 ? 2048 : 1024;
+  const int64_t p_max = 128;
+  int64_t P = std::min<int64_t>(p_max, ceil_div(N, tw_min));
+  int64_t Tw = ceil_div(ceil_div(N, P), 32) * 32;
+  P = ceil_div(N, Tw);
+  Tiling t;
+  t.P = (int)P;
+  t.Tw = (int)Tw;
+  t.Ta = (int)std::min<int64_t>(4096, ceil_div(N, 64) * 64);
+  return t;
+}
+
+// Bytes of the two matrix-core operand images of one head.
+size_t head_image_bytes(int D, int dt) {
+  const int idt = dt == LA_BF16 ? la::DT_BF16 : la::DT_FP32;
+  switch (D) {
+    case 16: return la::ImageCfg<16>::head_bytes(idt);
+    case 32: return la::ImageCfg<32>::head_bytes(idt);
+    case 64: return la::ImageCfg<64>::head_bytes(idt);
+    default: return la::ImageCfg<128>::head_bytes(idt);
+  }
+}
+
+struct Layout {
+  size_t part, S64, z64, img, stash, dS64, dz64, dimg, total;
+};
+
+// Forward: [part][S64][z64][img].
+// Backward: [img][part][stash][dS64][dz64][dimg]; the stash holds two floats
+// per query token (1/den, dden) between the query kernel and the dS
+// reduction, the only part of any workspace that grows with N.
+Layout layout_for(const la_attn_desc* d, int pass) {
+  const int64_t BH = d->B * d->H, D = d->d;
+  const Tiling t = choose_tiling(d->N, (int)D);
+  const size_t part = align_up((size_t)BH * t.P * (D * D + D) * sizeof(float));
+  const size_t mat = align_up((size_t)BH * D * D * sizeof(double));
+  const size_t vec = align_up((size_t)BH * D * sizeof(double));
+  const size_t img = align_up((size_t)BH * head_image_bytes((int)D, d->in_dtype));
+  Layout L{};
+  size_t off = 0;
+  if (pass == 0) {
+    L.part = off; off += part;
+    L.S64 = off; off += mat;
+    L.z64 = off; off += vec;
+    L.img = off; off += img;
+  } else {
+    L.img = off; off += img;
+    L.part = off; off += part;
+    L.stash = off; off += align_up((size_t)BH * d->N * 2 * sizeof(float));
+    L.dS64 = off; off += mat;
+    L.dz64 = off; off += vec;
+    L.dimg = off; off += img;
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* la_status_string(la_status s) {
+  switch (s) {
+    case LA_OK: return "LA_OK";
+    case LA_ERR_INVALID_ARG: return "LA_ERR_INVALID_ARG";
+    case LA_ERR_UNSUPPORTED: return "LA_ERR_UNSUPPORTED";
+    case LA_ERR_OOM: return "LA_ERR_OOM";
+    case LA_ERR_HIP: return "LA_ERR_HIP";
+    case LA_ERR_NOT_FOUND: return "LA_ERR_NOT_FOUND";
+    case LA_ERR_SHUTDOWN: return "LA_ERR_SHUTDOWN";
+    case LA_ERR_BUSY: return "LA_ERR_BUSY";
+  }
+  return "LA_ERR_UNKNOWN";
+}
+
+int32_t la_last_hip_error(void) { return g_last_hip_error; }
+
+la_status la_version(int32_t* major, int32_t* minor) {
+  if (!major || !minor) return LA_ERR_INVALID_ARG;
+  *major = 1;
+  *minor = 0;
+  return LA_OK;
+}
+
+la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* bytes) {
+  if (!bytes || (pass != 0 && pass != 1)) return LA_ERR_INVALID_ARG;
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  *bytes = layout_for(desc, pass).total;
+  return LA_OK;
+}
+
+la_status la_forward(const la_attn_desc* desc, const void* q, const void* k,
+                     const void* v, void* o, double* s_out, double* z_out,
+                     void* ws, size_t ws_bytes, la_stream stream) {
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  if (!q || !k || !v || !o || !ws) return LA_ERR_INVALID_ARG;
+  if (!aligned16(q) || !aligned16(k) || !aligned16(v) || !aligned16(o)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)s_out & 7u) || ((uintptr_t)z_out & 7u)) return LA_ERR_INVALID_ARG;
+  const Layout L = layout_for(desc, 0);
+  if (ws_bytes < L.total) return LA_ERR_OOM;
+  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  char* w = (char*)ws;
+  la::FwdArgs a{};
+  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
+  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
+  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
+  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
+  a.q = q; a.k = k; a.v = v; a.o = o;
+  a.P = t.P; a.Tw = t.Tw; a.Ta = t.Ta;
+  a.part = (float*)(w + L.part);
+  a.S64 = s_out ? s_out : (double*)(w + L.S64);
+  a.z64 = z_out ? z_out : (double*)(w + L.z64);
+  a.img = w + L.img;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = la::launch_forward(a);
+  if (e != hipSuccess) return hip_fail(e);
+  return LA_OK;
+}
+
+la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,
+                      const void* v, const double* s, const double* z,
+                      const void* dout, void* dq, void* dk, void* dv, void* ws,
+                      size_t ws_bytes, la_stream stream) {
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  if (!q || !k || !v || !s || !z || !dout || !dq || !dk || !dv || !ws) return LA_ERR_INVALID_ARG;
+  for (const void* p : {q, k, v, dout, (const void*)dq, (const void*)dk, (const void*)dv})
+    if (!aligned16(p)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)s & 7u) || ((uintptr_t)z & 7u)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
+  const Layout L = layout_for(desc, 1);
+  if (ws_bytes < L.total) return LA_ERR_OOM;
+  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  char* w = (char*)ws;
+  la::BwdArgs a{};
+  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
+  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
+  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
+  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
+  a.q = q; a.k = k; a.v = v; a.dout = dout;
+  a.dq = dq; a.dk = dk; a.dv = dv;
+  a.S64 = s; a.z64 = z;
+  a.P = t.P; a.Tw = t.Tw; a.Ta = t.Ta;
+  a.img = w + L.img;
+  a.part = (float*)(w + L.part);
+  a.stash = (float2*)(w + L.stash);
+  a.dS64 = (double*)(w + L.dS64);
+  a.dz64 = (double*)(w + L.dz64);
+  a.dimg = w + L.dimg;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = la::launch_backward(a);
+  if (e != hipSuccess) return hip_fail(e);
+  return LA_OK;
+}
+
+}  // extern "C"

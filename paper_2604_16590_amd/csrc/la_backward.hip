@@ -1,0 +1,402 @@
+// la_backward.hip -- gfx950 kernels of the backward pass.
+//
+// Gradients of L = <O, G> (G = dL/dO) for O_i = phi(q_i)^T S / den_i,
+// den_i = phi(q_i) . z:
+//   X_i    = S G_i                      (d-vector per query)
+//   G_i.O_i = phi(q_i) . X_i / den_i     (so O itself is never formed)
+//   dden_i = -(G_i . O_i) / den_i
+//   dQ_i   = (X_i / den_i + dden_i z) * phi'(q_i)
+//   dS     = sum_i phi(q_i) (G_i / den_i)^T,   dz = sum_i dden_i phi(q_i)
+//   dV_j   = dS^T phi(k_j),   dK_j = (dS v_j + dz) * phi'(k_j)
+// phi(Q) and phi(K) are recomputed from the inputs here, never stored by
+// the forward (the paper trains with activation recomputation, Sec. III-D).
+//
+// Passes: (1) images of S; (2) query kernel: dQ and per-token (1/den, dden);
+// (3) token reduction for dS, dz (the forward's summary kernel in its
+// backward mode); (4) FP64 combine of dS, dz; (5) key kernel: dK, dV.
+#include "la_kernels.h"
+#include "la_profile.h"
+
+namespace la {
+
+// Layout shared by the query and key kernels: lane (g, n) holds token n of
+// a 16-token tile and the contiguous feature run [g*Q4, g*Q4 + Q4); the
+// matrix-core results of A x (that run) land in the same lane and run.
+template <int DT, int D>
+struct RowCfg {
+  static constexpr int Q4 = D / 4;
+  static constexpr int NT = D / 16;
+  static constexpr int NS = ImageCfg<D>::NS;
+  static constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  static constexpr int RB = Q4 * ES;
+  static constexpr int RWD = RB >= 4 ? RB / 4 : 1;
+  static constexpr int TT = 2;  // 16-token tiles per operand read
+};
+
+// bf16 operand run: phi of the lane's features, packed, plus the rounded
+// values as floats and phi'.
+template <int DT, int D>
+__device__ __forceinline__ void phi_run(const uint32_t* w, bf16x8* ops, float* pr, float* dp) {
+  using C = RowCfg<DT, D>;
+  constexpr int Q4 = C::Q4;
+  if constexpr (DT == DT_BF16) {
+#pragma unroll
+    for (int s = 0; s < C::NS; ++s) {
+      u32x4 pk;
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const int c0 = 8 * s + 2 * pp;
+        if (c0 < Q4) {
+          const float x0 = word_elem<DT>(w, c0), x1 = word_elem<DT>(w, c0 + 1);
+          const float p0 = phi<DT>(x0), p1 = phi<DT>(x1);
+          pk[pp] = pack_bf16(p0, p1);
+          pr[c0] = bf16lo(pk[pp]);
+          pr[c0 + 1] = bf16hi(pk[pp]);
+          dp[c0] = x0 > 0.0f ? 1.0f : p0;
+          dp[c0 + 1] = x1 > 0.0f ? 1.0f : p1;
+        } else {
+          pk[pp] = 0;
+        }
+      }
+      ops[s] = as_bf16x8(pk);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < Q4; ++c) {
+      const float x = word_elem<DT>(w, c);
+      pr[c] = phi<DT>(x);
+      dp[c] = x > 0.0f ? 1.0f : pr[c];
+    }
+  }
+}
+
+// Raw bf16 words of a lane's run as matrix-core operands (zero padded).
+template <int D>
+__device__ __forceinline__ void raw_ops(const uint32_t* w, bf16x8* ops) {
+  constexpr int Q4 = D / 4;
+#pragma unroll
+  for (int s = 0; s < ImageCfg<D>::NS; ++s) {
+    u32x4 pk;
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      const int c0 = 8 * s + 2 * pp;
+      pk[pp] = c0 < Q4 ? w[c0 >> 1] : 0u;
+    }
+    ops[s] = as_bf16x8(pk);
+  }
+}
+
+// acc[i] += A_image[i] x B (the lane's run); bf16 images hold hi then lo
+// words per (tile, k-step); `use_lo` selects the two-part operand.
+template <int DT, int D, bool USE_LO>
+__device__ __forceinline__ void image_times_run(const u32x4* simg, int lane, const bf16x8* bops,
+                                                const float* bf, f32x4* acc) {
+  using C = RowCfg<DT, D>;
+  if constexpr (DT == DT_BF16) {
+#pragma unroll
+    for (int i = 0; i < C::NT; ++i) {
+#pragma unroll
+      for (int s = 0; s < C::NS; ++s) {
+        if constexpr (USE_LO) {
+          acc[i] = mfma_bf16(as_bf16x8(simg[((i * C::NS + s) * 2 + 0) * 64 + lane]), bops[s], acc[i]);
+          acc[i] = mfma_bf16(as_bf16x8(simg[((i * C::NS + s) * 2 + 1) * 64 + lane]), bops[s], acc[i]);
+        } else {
+          acc[i] = mfma_bf16(as_bf16x8(simg[(i * C::NS + s) * 64 + lane]), bops[s], acc[i]);
+        }
+      }
+      if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    constexpr int Q4 = C::Q4;
+#pragma unroll
+    for (int i = 0; i < C::NT; ++i) {
+#pragma unroll
+      for (int s4 = 0; s4 < Q4 / 4; ++s4) {
+        const u32x4 a = simg[(i * (Q4 / 4) + s4) * 64 + lane];
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) acc[i] = mfma_f32(__uint_as_float(a[t4]), bf[4 * s4 + t4], acc[i]);
+      }
+      if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int OT, int Q4>
+__device__ __forceinline__ void store_run(char* p, const float* x) {
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int OB = Q4 * OES;
+  constexpr int OW = OB >= 4 ? OB / 4 : 1;
+  uint32_t ow[OW];
+#pragma unroll
+  for (int c = 0; c < Q4; c += 2) {
+    if constexpr (OT == DT_BF16) {
+      ow[c >> 1] = pack_bf16(x[c], x[c + 1]);
+    } else {
+      ow[c] = __float_as_uint(x[c]);
+      ow[c + 1] = __float_as_uint(x[c + 1]);
+    }
+  }
+  store_words<OB>(p, ow);
+}
+
+// Copy `words` 16-byte words of an image into LDS; with `hi_only` only the
+// hi half of each (tile, k-step) pair of a bf16 image is kept.
+__device__ __forceinline__ void stage_image(u32x4* dst, const u32x4* src, int words, bool hi_only) {
+  for (int w = threadIdx.x; w < words; w += 256) {
+    if (hi_only) {
+      const int pair = w >> 6, lane = w & 63;
+      dst[w] = src[pair * 128 + lane];
+    } else {
+      dst[w] = src[w];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Query kernel: dQ, plus (1/den, dden) per token for the dS/dz reduction.
+// LDS holds the N image of S (A[row = q feature c][k = value feature e]).
+// ---------------------------------------------------------------------------
+template <int DT, int OT, int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_query_kernel(
+    const void* __restrict__ q, const void* __restrict__ dout, int64_t sb, int64_t sh,
+    int64_t sn, void* __restrict__ dq, int64_t osb, int64_t osh, int64_t osn, int H,
+    int64_t N, int Ta, const void* __restrict__ img, const double* __restrict__ z64,
+    float2* __restrict__ stash) {
+  using C = RowCfg<DT, D>;
+  using IC = ImageCfg<D>;
+  constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
+  __shared__ u32x4 simg[IMG_WORDS];
+
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  stage_image(simg, (const u32x4*)((const char*)img + (int64_t)bh * IC::head_bytes(DT) +
+                                   IC::img_bytes(DT)),
+              IMG_WORDS, false);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  double zr[Q4];
+#pragma unroll
+  for (int c = 0; c < Q4; ++c) zr[c] = z64[(int64_t)bh * D + g * Q4 + c];
+  __syncthreads();
+
+  const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
+  const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
+  const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * C::RB;
+  const char* qbase = (const char*)q + in_head;
+  const char* gbase = (const char*)dout + in_head;
+  char* obase = (char*)dq + (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
+
+  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
+    uint32_t qw[TT][C::RWD], gw[TT][C::RWD];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const int64_t t = t0 + 16 * tt + n;
+      if (t < wg_end) {
+        load_words<C::RB>(qbase + t * sn * C::ES, qw[tt]);
+        load_words<C::RB>(gbase + t * sn * C::ES, gw[tt]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < C::RWD; ++w) { qw[tt][w] = 0; gw[tt][w] = 0; }
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      bf16x8 gops[C::NS], qops[C::NS];
+      float pr[Q4], dp[Q4], gf[Q4];
+      phi_run<DT, D>(qw[tt], qops, pr, dp);
+      if constexpr (DT == DT_BF16) {
+        raw_ops<D>(gw[tt], gops);
+      } else {
+#pragma unroll
+        for (int c = 0; c < Q4; ++c) gf[c] = __uint_as_float(gw[tt][c]);
+      }
+      f32x4 acc[NT];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      image_times_run<DT, D, true>(simg, lane, gops, gf, acc);  // X = S G
+      double den = 0.0, gn = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = 4 * i + r;
+          den = fma((double)pr[c], zr[c], den);
+          gn = fma((double)pr[c], (double)acc[i][r], gn);
+        }
+      den = sum_groups(den);
+      gn = sum_groups(gn);
+      const double rden = 1.0 / den;
+      const double go = gn * rden;  // G . O
+      const int64_t t = t0 + 16 * tt + n;
+      if (t < wg_end) {
+        float out[Q4];
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = 4 * i + r;
+            out[c] = (float)(fma(-go, zr[c], (double)acc[i][r]) * rden) * dp[c];
+          }
+        store_run<OT, Q4>(obase + t * osn * OES, out);
+        if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go * rden)};
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Key kernel: dV = phi(K) dS (T image of dS) and dK = (V dS^T + dz) phi'(K)
+// (N image of dS).  WHICH: 1 = dV only, 2 = dK only, 3 = both.
+// The dS operands are the hi parts of the bf16 images.
+// ---------------------------------------------------------------------------
+template <int DT, int OT, int D, int WHICH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_key_kernel(
+    const void* __restrict__ k, const void* __restrict__ v, int64_t sb, int64_t sh,
+    int64_t sn, void* __restrict__ dk, void* __restrict__ dv, int64_t osb, int64_t osh,
+    int64_t osn, int H, int64_t N, int Ta, const void* __restrict__ dimg,
+    const double* __restrict__ dz64) {
+  using C = RowCfg<DT, D>;
+  using IC = ImageCfg<D>;
+  constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int ONE = DT == DT_BF16 ? IC::img_bytes(DT) / 32 : IC::img_bytes(DT) / 16;
+  constexpr bool DO_V = WHICH & 1, DO_K = WHICH & 2;
+  __shared__ u32x4 simg[(DO_V ? ONE : 0) + (DO_K ? ONE : 0)];
+  u32x4* timg = simg;
+  u32x4* nimg = simg + (DO_V ? ONE : 0);
+
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  const u32x4* head = (const u32x4*)((const char*)dimg + (int64_t)bh * IC::head_bytes(DT));
+  if (DO_V) stage_image(timg, head, ONE, DT == DT_BF16);
+  if (DO_K) stage_image(nimg, head + IC::img_bytes(DT) / 16, ONE, DT == DT_BF16);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  double dzr[DO_K ? Q4 : 1];
+  if constexpr (DO_K) {
+#pragma unroll
+    for (int c = 0; c < Q4; ++c) dzr[c] = dz64[(int64_t)bh * D + g * Q4 + c];
+  }
+  __syncthreads();
+
+  const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
+  const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
+  const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * C::RB;
+  const char* kbase = (const char*)k + in_head;
+  const char* vbase = (const char*)v + in_head;
+  const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
+
+  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
+    uint32_t kw[TT][C::RWD], vw[TT][C::RWD];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const int64_t t = t0 + 16 * tt + n;
+      if (t < wg_end) {
+        load_words<C::RB>(kbase + t * sn * C::ES, kw[tt]);
+        if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw[tt]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < C::RWD; ++w) { kw[tt][w] = 0; vw[tt][w] = 0; }
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      bf16x8 kops[C::NS], vops[C::NS];
+      float pr[Q4], dp[Q4], vf[Q4];
+      phi_run<DT, D>(kw[tt], kops, pr, dp);
+      const int64_t t = t0 + 16 * tt + n;
+      if constexpr (DO_V) {
+        f32x4 acc[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        image_times_run<DT, D, false>(timg, lane, kops, pr, acc);
+        if (t < wg_end) {
+          float out[Q4];
+#pragma unroll
+          for (int i = 0; i < NT; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[4 * i + r] = acc[i][r];
+          store_run<OT, Q4>((char*)dv + out_head + t * osn * OES, out);
+        }
+      }
+      if constexpr (DO_K) {
+        if constexpr (DT == DT_BF16) {
+          raw_ops<D>(vw[tt], vops);
+        } else {
+#pragma unroll
+          for (int c = 0; c < Q4; ++c) vf[c] = __uint_as_float(vw[tt][c]);
+        }
+        f32x4 acc[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        image_times_run<DT, D, false>(nimg, lane, vops, vf, acc);
+        if (t < wg_end) {
+          float out[Q4];
+#pragma unroll
+          for (int i = 0; i < NT; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int c = 4 * i + r;
+              out[c] = (float)((double)acc[i][r] + dzr[c]) * dp[c];
+            }
+          store_run<OT, Q4>((char*)dk + out_head + t * osn * OES, out);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int DT, int OT, int D>
+static void launch_rows(const BwdArgs& a) {
+  const int BH = (int)(a.B * a.H);
+  dim3 grid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
+  {
+    ProfScope prof("bwd_query", a.stream);
+    bwd_query_kernel<DT, OT, D><<<grid, 256, 0, a.stream>>>(
+        a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img,
+        a.z64, a.stash);
+  }
+  launch_summary(MODE_BWD, DT, D, a.q, a.dout, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
+                 a.stash, a.part, a.stream);
+  launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, a.stream);
+  // both dS images fit in LDS except fp32 at d = 128 (2 x 64 KB): two passes
+  ProfScope prof("bwd_key", a.stream);
+  if constexpr (DT == DT_FP32 && D >= 128) {
+    bwd_key_kernel<DT, OT, D, 1><<<grid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+        a.dimg, a.dz64);
+    bwd_key_kernel<DT, OT, D, 2><<<grid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+        a.dimg, a.dz64);
+  } else {
+    bwd_key_kernel<DT, OT, D, 3><<<grid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+        a.dimg, a.dz64);
+  }
+}
+
+template <int D>
+static hipError_t launch_backward_d(const BwdArgs& a) {
+  hipError_t e = launch_images(a.S64, a.img, a.in_dt, a.B * a.H, D, a.stream);
+  if (e != hipSuccess) return e;
+  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) launch_rows<DT_BF16, DT_BF16, D>(a);
+  else if (a.in_dt == DT_BF16) launch_rows<DT_BF16, DT_FP32, D>(a);
+  else if (a.out_dt == DT_BF16) launch_rows<DT_FP32, DT_BF16, D>(a);
+  else launch_rows<DT_FP32, DT_FP32, D>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const BwdArgs& a) {
+  switch (a.D) {
+    case 16: return launch_backward_d<16>(a);
+    case 32: return launch_backward_d<32>(a);
+    case 64: return launch_backward_d<64>(a);
+    case 128: return launch_backward_d<128>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace la

@@ -1,0 +1,495 @@
+// la_forward.hip -- gfx950 kernels of the forward pass and of the FP64
+// cross-tile combine.
+//
+// Forward of kernelised linear attention per (b, h):
+//   S = phi(K)^T V, z = phi(K)^T 1 over all N tokens (summary_kernel, then
+//   combine_kernel), O_i = phi(q_i)^T S / (phi(q_i) . z) (apply_kernel).
+// Both phases stream HBM once: summary reads K and V, apply reads Q and
+// writes O.  The d x d contractions run on the matrix cores.
+#include "la_kernels.h"
+#include "la_profile.h"
+
+namespace la {
+
+// ---------------------------------------------------------------------------
+// Summary: per wave, a contiguous token range [p*Tw, p*Tw + Tw) of one head.
+// Lane (g, m) owns key/value features [F*m, F*m + F) (F = d/16) of R tokens
+// per lane group per step.  Loads are contiguous F-feature runs of a token,
+// so one load instruction covers whole token rows.  The feature-major
+// operands the matrix core needs (a token run per feature) are assembled in
+// registers: for bf16 the two tokens of a pair are packed into one word, so
+// the transpose costs nothing beyond the pack that rounds phi(k) anyway.
+//
+// Tile (i, j) of the accumulator holds rows m <-> key feature F*m + i and
+// columns n <-> value feature F*n + j, so lane (g, n) ends with
+//   S[F*(4g + r) + i][F*n + j],  r = 0..3.
+// These FP32 per-wave sums are written out; combine_kernel adds them in
+// FP64 in partial order.
+// ---------------------------------------------------------------------------
+template <int DT, int D>
+struct SummaryCfg {
+  static constexpr int F = D / 16;                 // features per lane (S tile grid is F x F)
+  static constexpr int SPLIT = D >= 128 ? 2 : 1;   // waves sharing one token range
+  static constexpr int FR = F / SPLIT;             // S tile rows per wave
+  static constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  static constexpr int KB = FR * ES;               // key bytes per lane per token
+  static constexpr int VB = F * ES;                // value bytes per lane per token
+  static constexpr int KW = KB >= 4 ? KB / 4 : 1;
+  static constexpr int VW = VB >= 4 ? VB / 4 : 1;
+  static constexpr int R = DT == DT_BF16 ? 8 : 4;  // tokens per lane group per step
+  static constexpr int STEP = 4 * R;               // tokens per wave per step
+  static constexpr int PPB = 4 / SPLIT;            // partials per 4-wave block
+};
+
+// Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
+// they add exactly nothing to S or z and the step itself needs no masks.
+// In the backward mode the per-token pair (1/den, dden) is loaded too.
+template <int DT, int D, int MODE>
+__device__ __forceinline__ void summary_load(const char* kp, const char* vp,
+                                             const float2* stash,
+                                             int64_t row_bytes, int64_t t0, int g,
+                                             int64_t t_end, bool partial,
+                                             uint32_t (&kw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::KW],
+                                             uint32_t (&vw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::VW],
+                                             float2 (&tok)[SummaryCfg<DT, D>::R]) {
+  using C = SummaryCfg<DT, D>;
+  const uint32_t neg_inf = DT == DT_BF16 ? 0xff80ff80u : 0xff800000u;
+#pragma unroll
+  for (int r = 0; r < C::R; ++r) {
+    const int64_t t = t0 + C::R * g + r;
+    if (!partial || t < t_end) {
+      load_words<C::KB>(kp + t * row_bytes, kw[r]);
+      load_words<C::VB>(vp + t * row_bytes, vw[r]);
+      if constexpr (MODE == MODE_BWD) tok[r] = stash[t];
+    } else {
+#pragma unroll
+      for (int w = 0; w < C::KW; ++w) kw[r][w] = neg_inf;
+#pragma unroll
+      for (int w = 0; w < C::VW; ++w) vw[r][w] = 0;
+      if constexpr (MODE == MODE_BWD) tok[r] = float2{0.f, 0.f};
+    }
+  }
+}
+
+// One step of the summary: phi on the keys, register transpose, MFMAs.
+// MODE_FWD: rows = phi(k), columns = v, z += phi(k).
+// MODE_BWD: rows = phi(q), columns = dO / den, z += dden * phi(q), which
+// accumulates dS and dz of the backward pass.
+template <int DT, int D, int MODE>
+__device__ __forceinline__ void summary_step(
+    const uint32_t (&kw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::KW],
+    const uint32_t (&vw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::VW],
+    const float2 (&tok)[SummaryCfg<DT, D>::R],
+    f32x4 (&acc)[SummaryCfg<DT, D>::FR][SummaryCfg<DT, D>::F],
+    float (&zacc)[SummaryCfg<DT, D>::FR]) {
+  using C = SummaryCfg<DT, D>;
+  constexpr int F = C::F, FR = C::FR;
+  if constexpr (DT == DT_BF16) {
+    // Value operands: token pairs of one feature packed into words.
+    bf16x8 bv[F];
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      u32x4 w;
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        if constexpr (MODE == MODE_FWD) {
+          const uint32_t lo = word_bits16<DT>(vw[2 * pp], j);
+          const uint32_t hi = word_bits16<DT>(vw[2 * pp + 1], j);
+          w[pp] = lo | (hi << 16);
+        } else {
+          w[pp] = pack_bf16(word_elem<DT>(vw[2 * pp], j) * tok[2 * pp].x,
+                            word_elem<DT>(vw[2 * pp + 1], j) * tok[2 * pp + 1].x);
+        }
+      }
+      bv[j] = as_bf16x8(w);
+    }
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      uint32_t pk[4];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const float p0 = phi<DT>(word_elem<DT>(kw[2 * pp], i));
+        const float p1 = phi<DT>(word_elem<DT>(kw[2 * pp + 1], i));
+        pk[pp] = pack_bf16(p0, p1);
+        if constexpr (MODE == MODE_FWD) {
+          // normaliser from the same rounded phi values that feed S
+          zacc[i] = add_bf16_pair(zacc[i], pk[pp]);
+        } else {
+          zacc[i] = fmaf(tok[2 * pp].y, bf16lo(pk[pp]), zacc[i]);
+          zacc[i] = fmaf(tok[2 * pp + 1].y, bf16hi(pk[pp]), zacc[i]);
+        }
+      }
+      const bf16x8 ak = as_bf16x8(u32x4{pk[0], pk[1], pk[2], pk[3]});
+#pragma unroll
+      for (int j = 0; j < F; ++j) acc[i][j] = mfma_bf16(ak, bv[j], acc[i][j]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < C::R; ++r) {
+      float pk[FR];
+#pragma unroll
+      for (int i = 0; i < FR; ++i) {
+        pk[i] = phi<DT>(word_elem<DT>(kw[r], i));
+        if constexpr (MODE == MODE_FWD) zacc[i] += pk[i];
+        else zacc[i] = fmaf(tok[r].y, pk[i], zacc[i]);
+      }
+      float vv[F];
+#pragma unroll
+      for (int j = 0; j < F; ++j) {
+        vv[j] = word_elem<DT>(vw[r], j);
+        if constexpr (MODE == MODE_BWD) vv[j] *= tok[r].x;
+      }
+#pragma unroll
+      for (int i = 0; i < FR; ++i)
+#pragma unroll
+        for (int j = 0; j < F; ++j)
+          acc[i][j] = mfma_f32(pk[i], vv[j], acc[i][j]);
+    }
+  }
+}
+
+// Grid: x = blocks of PPB partials, y = (b, h).  Wave w of a block takes
+// partial p = x*PPB + w/SPLIT and S tile rows [FR*(w%SPLIT), +FR).
+template <int DT, int D, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void summary_kernel(
+    const void* __restrict__ k, const void* __restrict__ v, int64_t sb,
+    int64_t sh, int64_t sn, int H, int64_t N, int P, int Tw,
+    const float2* __restrict__ stash, float* __restrict__ part) {
+  using C = SummaryCfg<DT, D>;
+  constexpr int F = C::F, FR = C::FR;
+  constexpr int E = D * D + D;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  const int p = blockIdx.x * C::PPB + wave / C::SPLIT;
+  const int half = wave % C::SPLIT;
+  if (p >= P) return;
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  const int64_t t_begin = (int64_t)p * Tw;
+  const int64_t t_end = min(N, t_begin + (int64_t)Tw);
+  const int64_t head = (b * sb + h * sh) * C::ES;
+  // lane m reads key features [F*m + FR*half, +FR) and value features [F*m, +F)
+  const char* kp = (const char*)k + head + (int64_t)(F * m + FR * half) * C::ES;
+  const char* vp = (const char*)v + head + (int64_t)m * C::VB;
+  const int64_t row_bytes = sn * C::ES;
+
+  f32x4 acc[FR][F];
+#pragma unroll
+  for (int i = 0; i < FR; ++i)
+#pragma unroll
+    for (int j = 0; j < F; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float zacc[FR];
+#pragma unroll
+  for (int i = 0; i < FR; ++i) zacc[i] = 0.f;
+
+  const float2* tstash = MODE == MODE_BWD ? stash + (int64_t)bh * N : nullptr;
+  for (int64_t t0 = t_begin; t0 < t_end; t0 += C::STEP) {
+    uint32_t kw[C::R][C::KW], vw[C::R][C::VW];
+    float2 tok[C::R];
+    summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0, g, t_end, t0 + C::STEP > t_end, kw, vw, tok);
+    summary_step<DT, D, MODE>(kw, vw, tok, acc, zacc);
+  }
+
+  // this wave's share of the partial: S tiles in lane order, then z
+  float* out = part + ((int64_t)bh * P + p) * E;
+#pragma unroll
+  for (int il = 0; il < FR; ++il) {
+    const int i = FR * half + il;
+#pragma unroll
+    for (int j = 0; j < F; ++j)
+      *(f32x4*)(out + ((i * F + j) * 64 + lane) * 4) = acc[il][j];
+  }
+#pragma unroll
+  for (int il = 0; il < FR; ++il) {
+    const float zs = sum_groups(zacc[il]);
+    if (g == 0) out[D * D + F * m + FR * half + il] = zs;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Combine: FP64 sum of the P per-wave partials in partial order (fixed, so
+// results are bitwise reproducible), writing the dense FP64 matrix M
+// (S or dS) and vector (z or dz), plus the matrix-core operand images.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void combine_kernel(
+    const float* __restrict__ part, int P, double* __restrict__ M64,
+    double* __restrict__ v64, void* __restrict__ img, int img_dt) {
+  constexpr int F = D / 16;
+  constexpr int E = D * D + D;
+  const int bh = blockIdx.y;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= E) return;
+  const float* src = part + (int64_t)bh * P * E + u;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += (double)src[(int64_t)p * E];
+  if (u < D * D) {
+    const int r = u & 3, lane = (u >> 2) & 63, ij = u >> 8;
+    const int i = ij / F, j = ij % F;
+    const int g = lane >> 4, n = lane & 15;
+    const int c = F * (4 * g + r) + i, e = F * n + j;
+    M64[(int64_t)bh * D * D + c * D + e] = s;
+    write_images<D>(img, img_dt, bh, c, e, s);
+  } else {
+    v64[(int64_t)bh * D + (u - D * D)] = s;
+  }
+}
+
+// Images from a dense FP64 matrix (used when S comes from the caller).
+template <int D>
+__global__ __launch_bounds__(256) void image_kernel(const double* __restrict__ M64,
+                                                    void* __restrict__ img, int img_dt) {
+  const int bh = blockIdx.y;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u >= D * D) return;
+  write_images<D>(img, img_dt, bh, u / D, u % D, M64[(int64_t)bh * D * D + u]);
+}
+
+// ---------------------------------------------------------------------------
+// Apply: O^T = S^T phi(Q)^T per 16-token tile.  Lane (g, n) holds token n
+// and query features [g*Q4, g*Q4 + Q4) (Q4 = d/4), read as one contiguous
+// run; the matrix-core result puts value features [g*Q4, g*Q4 + Q4) of the
+// same token in the same lane, so the normaliser, the FP64 division and the
+// store all stay in-lane.  The S^T operands (bf16 hi + lo parts, or fp32)
+// sit in LDS for the whole workgroup.
+// ---------------------------------------------------------------------------
+template <int DT, int OT, int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void apply_kernel(
+    const void* __restrict__ q, int64_t sb, int64_t sh, int64_t sn,
+    void* __restrict__ o, int64_t osb, int64_t osh, int64_t osn, int H,
+    int64_t N, int Ta, const void* __restrict__ img,
+    const double* __restrict__ z64) {
+  using IC = ImageCfg<D>;
+  constexpr int Q4 = D / 4;
+  constexpr int NT = D / 16;
+  constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int QB = Q4 * ES;                 // bytes of a lane's query run
+  constexpr int QW = QB >= 4 ? QB / 4 : 1;
+  constexpr int OB = Q4 * OES;
+  constexpr int OW = OB >= 4 ? OB / 4 : 1;
+  constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
+  constexpr int TT = 2;                       // 16-token tiles per operand read
+  __shared__ u32x4 simg[IMG_WORDS];
+
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  {
+    // the T image (first of the head's two) holds S^T operands
+    const u32x4* src = (const u32x4*)((const char*)img + (int64_t)bh * IC::head_bytes(DT));
+    for (int w = threadIdx.x; w < IMG_WORDS; w += 256) simg[w] = src[w];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  double zr[Q4];
+#pragma unroll
+  for (int c = 0; c < Q4; ++c) zr[c] = z64[(int64_t)bh * D + g * Q4 + c];
+  __syncthreads();
+
+  const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
+  const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
+  const char* qbase = (const char*)q + (b * sb + h * sh) * ES + (int64_t)g * QB;
+  char* obase = (char*)o + (b * osb + h * osh) * OES + (int64_t)g * OB;
+
+  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
+    uint32_t qw[TT][QW];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const int64_t t = t0 + 16 * tt + n;
+      if (t < wg_end) {
+        load_words<QB>(qbase + t * sn * ES, qw[tt]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
+      }
+    }
+    // phi(q), the FP64 normaliser, and the matrix-core operands
+    double den[TT];
+    f32x4 acc[TT][NT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      den[tt] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if constexpr (DT == DT_BF16) {
+      constexpr int NS = IC::NS;
+      bf16x8 bq[TT][NS];
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          u32x4 w;
+#pragma unroll
+          for (int pp = 0; pp < 4; ++pp) {
+            const int c0 = 8 * s + 2 * pp;
+            if (c0 < Q4) {
+              const float p0 = phi<DT>(word_elem<DT>(qw[tt], c0));
+              const float p1 = phi<DT>(word_elem<DT>(qw[tt], c0 + 1));
+              w[pp] = pack_bf16(p0, p1);
+              den[tt] = fma((double)bf16lo(w[pp]), zr[c0], den[tt]);
+              den[tt] = fma((double)bf16hi(w[pp]), zr[c0 + 1], den[tt]);
+            } else {
+              w[pp] = 0;
+            }
+          }
+          bq[tt][s] = as_bf16x8(w);
+        }
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const bf16x8 hi = as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]);
+          const bf16x8 lo = as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]);
+#pragma unroll
+          for (int tt = 0; tt < TT; ++tt) {
+            acc[tt][i] = mfma_bf16(hi, bq[tt][s], acc[tt][i]);
+            acc[tt][i] = mfma_bf16(lo, bq[tt][s], acc[tt][i]);
+          }
+          // keep the operand reads next to their use (bounded registers)
+          if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+      float pq[TT][Q4];
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+        for (int c = 0; c < Q4; ++c) {
+          pq[tt][c] = phi<DT>(word_elem<DT>(qw[tt], c));
+          den[tt] = fma((double)pq[tt][c], zr[c], den[tt]);
+        }
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int s4 = 0; s4 < Q4 / 4; ++s4) {
+          const u32x4 a = simg[(i * (Q4 / 4) + s4) * 64 + lane];
+#pragma unroll
+          for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt)
+              acc[tt][i] = mfma_f32(__uint_as_float(a[t4]), pq[tt][4 * s4 + t4], acc[tt][i]);
+          if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const double rden = 1.0 / sum_groups(den[tt]);
+      const int64_t t = t0 + 16 * tt + n;
+      if (t < wg_end) {
+        uint32_t ow[OW];
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            // O = num / den: FP64 reciprocal of the FP64 normaliser, FP64 product
+            const float o0 = (float)((double)acc[tt][i][r] * rden);
+            const float o1 = (float)((double)acc[tt][i][r + 1] * rden);
+            const int e = 4 * i + r;  // position in the lane's output run
+            if constexpr (OT == DT_BF16) {
+              ow[e >> 1] = pack_bf16(o0, o1);
+            } else {
+              ow[e] = __float_as_uint(o0);
+              ow[e + 1] = __float_as_uint(o1);
+            }
+          }
+        store_words<OB>(obase + t * osn * OES, ow);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <int D>
+static void launch_summary_d(int mode, int dt, const void* k, const void* v, int64_t sb,
+                             int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
+                             int Tw, const float2* stash, float* part, hipStream_t stream) {
+  constexpr int PPB = D >= 128 ? 2 : 4;  // SummaryCfg<*, D>::PPB
+  dim3 grid((P + PPB - 1) / PPB, (unsigned)(B * H));
+  ProfScope prof(mode == MODE_FWD ? "summary_fwd" : "summary_bwd", stream);
+#define LA_SUM(DTI, M) \
+  summary_kernel<DTI, D, M><<<grid, 256, 0, stream>>>(k, v, sb, sh, sn, (int)H, N, P, Tw, stash, part)
+  if (mode == MODE_FWD) {
+    if (dt == DT_BF16) LA_SUM(DT_BF16, MODE_FWD); else LA_SUM(DT_FP32, MODE_FWD);
+  } else {
+    if (dt == DT_BF16) LA_SUM(DT_BF16, MODE_BWD); else LA_SUM(DT_FP32, MODE_BWD);
+  }
+#undef LA_SUM
+}
+
+hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v, int64_t sb,
+                          int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
+                          int Tw, const float2* stash, float* part, hipStream_t stream) {
+  switch (D) {
+    case 16: launch_summary_d<16>(mode, dt, k, v, sb, sh, sn, B, H, N, P, Tw, stash, part, stream); break;
+    case 32: launch_summary_d<32>(mode, dt, k, v, sb, sh, sn, B, H, N, P, Tw, stash, part, stream); break;
+    case 64: launch_summary_d<64>(mode, dt, k, v, sb, sh, sn, B, H, N, P, Tw, stash, part, stream); break;
+    case 128: launch_summary_d<128>(mode, dt, k, v, sb, sh, sn, B, H, N, P, Tw, stash, part, stream); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
+                          int img_dt, int64_t BH, int D, hipStream_t stream) {
+  dim3 grid((D * D + D + 255) / 256, (unsigned)BH);
+  ProfScope prof("combine", stream);
+  switch (D) {
+    case 16: combine_kernel<16><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
+    case 32: combine_kernel<32><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
+    case 64: combine_kernel<64><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
+    case 128: combine_kernel<128><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_forward_d(const FwdArgs& a) {
+  const int BH = (int)(a.B * a.H);
+  launch_summary_d<D>(MODE_FWD, a.in_dt, a.k, a.v, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
+                      nullptr, a.part, a.stream);
+  {
+    dim3 cgrid((D * D + D + 255) / 256, BH);
+    ProfScope prof("combine", a.stream);
+    combine_kernel<D><<<cgrid, 256, 0, a.stream>>>(a.part, a.P, a.S64, a.z64, a.img, a.in_dt);
+  }
+  dim3 agrid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
+  ProfScope prof("apply", a.stream);
+#define LA_APPLY(DTI, DTO)                                                       \
+  apply_kernel<DTI, DTO, D><<<agrid, 256, 0, a.stream>>>(                         \
+      a.q, a.sb, a.sh, a.sn, a.o, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img, a.z64)
+  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) LA_APPLY(DT_BF16, DT_BF16);
+  else if (a.in_dt == DT_BF16) LA_APPLY(DT_BF16, DT_FP32);
+  else if (a.out_dt == DT_BF16) LA_APPLY(DT_FP32, DT_BF16);
+  else LA_APPLY(DT_FP32, DT_FP32);
+#undef LA_APPLY
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs& a) {
+  switch (a.D) {
+    case 16: return launch_forward_d<16>(a);
+    case 32: return launch_forward_d<32>(a);
+    case 64: return launch_forward_d<64>(a);
+    case 128: return launch_forward_d<128>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_images(const double* M64, void* img, int img_dt, int64_t BH, int D,
+                         hipStream_t stream) {
+  dim3 grid((D * D + 255) / 256, (unsigned)BH);
+  ProfScope prof("images", stream);
+  switch (D) {
+    case 16: image_kernel<16><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
+    case 32: image_kernel<32><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
+    case 64: image_kernel<64><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
+    case 128: image_kernel<128><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace la

@@ -1,0 +1,121 @@
+// la_kernels.h -- launch arguments, operand-image layout and launcher
+// declarations of the gfx950 kernels (internal to liblinattn).
+#pragma once
+#include "la_device.h"
+
+namespace la {
+
+// Matrix-core operand images of a d x d matrix M (S or dS), per head.
+// Two images per head:
+//   T image: A[row = value feature e][k = key/query feature c] = M[c][e]
+//   N image: A[row = key/query feature c][k = value feature e] = M[c][e]
+// A 16-row output tile i maps row m to feature (m/4)*Q4 + 4i + (m%4), so a
+// lane's four result rows over all tiles cover one contiguous run of Q4
+// features.  The contraction index k maps to lane group g' = k / Q4 and
+// position k % Q4 inside that group's run, matching how the B operand
+// (one token per lane, a contiguous feature run per lane group) is loaded.
+// bf16 images store a hi part bf16(M) and a lo part bf16(M - hi); fp32
+// images store float(M).
+template <int D>
+struct ImageCfg {
+  static constexpr int Q4 = D / 4;
+  static constexpr int NT = D / 16;                  // output tiles
+  static constexpr int NS = D >= 32 ? D / 32 : 1;    // bf16 k-steps of 32
+  static constexpr int BF16_BYTES = NT * NS * 2 * 64 * 16;  // one image
+  static constexpr int F32_BYTES = NT * (Q4 / 4) * 64 * 16;
+  static constexpr int img_bytes(int dt) { return dt == DT_BF16 ? BF16_BYTES : F32_BYTES; }
+  static constexpr int head_bytes(int dt) { return 2 * img_bytes(dt); }
+};
+
+template <int D>
+__device__ __forceinline__ void image_slot(int row, int k, int& word, int& slot, int dt) {
+  using IC = ImageCfg<D>;
+  constexpr int Q4 = IC::Q4;
+  const int gq = row / Q4, rrem = row % Q4;
+  const int i = rrem >> 2, m = 4 * gq + (rrem & 3);
+  const int gk = k / Q4, krem = k % Q4;
+  const int lane = 16 * gk + m;
+  if (dt == DT_BF16) {
+    const int s = krem >> 3;
+    slot = krem & 7;
+    word = ((i * IC::NS + s) * 2) * 64 + lane;  // hi part; lo part is +64
+  } else {
+    slot = krem & 3;
+    word = (i * (Q4 / 4) + (krem >> 2)) * 64 + lane;
+  }
+}
+
+// Store M[c][e] = val into both images of head bh.
+template <int D>
+__device__ __forceinline__ void write_images(void* img, int dt, int bh, int c, int e, double val) {
+  using IC = ImageCfg<D>;
+  char* head = (char*)img + (int64_t)bh * IC::head_bytes(dt);
+  for (int which = 0; which < 2; ++which) {
+    const int row = which == 0 ? e : c;
+    const int k = which == 0 ? c : e;
+    int word, slot;
+    image_slot<D>(row, k, word, slot, dt);
+    char* base = head + which * IC::img_bytes(dt);
+    if (dt == DT_BF16) {
+      const uint16_t hi = to_bf16((float)val);
+      const uint16_t lo = to_bf16((float)(val - (double)bf16f(hi)));
+      uint16_t* wh = (uint16_t*)(base + (int64_t)word * 16);
+      uint16_t* wl = (uint16_t*)(base + (int64_t)(word + 64) * 16);
+      wh[slot] = hi;
+      wl[slot] = lo;
+      if (IC::Q4 < 8) {  // d = 16: slots 4..7 of each k-step are padding
+        wh[slot + 4] = 0;
+        wl[slot + 4] = 0;
+      }
+    } else {
+      ((float*)(base + (int64_t)word * 16))[slot] = (float)val;
+    }
+  }
+}
+
+struct FwdArgs {
+  int64_t B, H, N;
+  int D, in_dt, out_dt;
+  int64_t sb, sh, sn, osb, osh, osn;
+  const void *q, *k, *v;
+  void* o;
+  int P, Tw, Ta;       // partials per head, tokens per partial, tokens per apply workgroup
+  float* part;         // [BH][P][D*D + D]
+  double* S64;         // [BH][D][D]
+  double* z64;         // [BH][D]
+  void* img;           // [BH][2 images]
+  hipStream_t stream;
+};
+
+struct BwdArgs {
+  int64_t B, H, N;
+  int D, in_dt, out_dt;
+  int64_t sb, sh, sn, osb, osh, osn;
+  const void *q, *k, *v, *dout;
+  void *dq, *dk, *dv;
+  const double *S64, *z64;
+  int P, Tw, Ta;
+  void* img;           // images of S
+  float* part;         // partials of dS, dz
+  float2* stash;       // [BH][N] per query token: (1/den, dden)
+  double* dS64;
+  double* dz64;
+  void* dimg;          // images of dS
+  hipStream_t stream;
+};
+
+enum { MODE_FWD = 0, MODE_BWD = 1 };
+
+hipError_t launch_forward(const FwdArgs& a);
+// Token-reduction kernel: forward summary (MODE_FWD) or the dS/dz sums of
+// the backward (MODE_BWD, k = Q, v = dO, stash = per-token (1/den, dden)).
+hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v, int64_t sb,
+                          int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
+                          int Tw, const float2* stash, float* part, hipStream_t stream);
+hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
+                          int img_dt, int64_t BH, int D, hipStream_t stream);
+hipError_t launch_backward(const BwdArgs& a);
+hipError_t launch_images(const double* M64, void* img, int img_dt, int64_t BH, int D,
+                         hipStream_t stream);
+
+}  // namespace la

@@ -1,0 +1,110 @@
+"""The C-ABI libraries load and export every declared symbol, and argument
+checking rejects bad descriptors before any GPU work (runs without a GPU)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_2604_16590_amd as la
+from paper_2604_16590_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(la_[a-z_0-9]+)\s*\(", text, re.M))
+
+
+@pytest.mark.parametrize("header,lib", [("la.h", B.LIB_PATH), ("la_gen.h", B.GEN_PATH)])
+def test_every_declared_symbol_is_exported(header, lib):
+    names = declared(os.path.join(ROOT, "include", header))
+    assert names, header
+    handle = ctypes.CDLL(lib)
+    missing = [n for n in sorted(names) if not hasattr(handle, n)]
+    assert not missing, missing
+
+
+def test_headers_cover_all_exports():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        names |= declared(h)
+    assert {"la_forward", "la_backward", "la_workspace_size", "la_gen_fill"} <= names
+
+
+def desc(**kw):
+    d = dict(B=1, H=2, N=100, d=64, in_dtype=0, out_dtype=0, in_sb=2 * 100 * 64, in_sh=100 * 64,
+             in_sn=64, out_sb=2 * 100 * 64, out_sh=100 * 64, out_sn=64, feature_map=0, flags=0)
+    d.update(kw)
+    return B.AttnDesc(**d)
+
+
+def ws_status(dsc, pass_=0):
+    n = ctypes.c_size_t(0)
+    return la.lib().la_workspace_size(ctypes.byref(dsc), pass_, ctypes.byref(n)), n.value
+
+
+def test_status_strings():
+    L = la.lib()
+    assert L.la_status_string(0) == b"LA_OK"
+    assert L.la_status_string(2) == b"LA_ERR_UNSUPPORTED"
+    assert L.la_status_string(99) == b"LA_ERR_UNKNOWN"
+
+
+def test_workspace_size_valid_and_bounded_in_N():
+    st, small = ws_status(desc(N=1 << 16))
+    assert st == 0 and small > 0
+    st, big = ws_status(desc(N=1 << 30, in_sb=2 * (1 << 30) * 64, in_sh=(1 << 30) * 64,
+                             out_sb=2 * (1 << 30) * 64, out_sh=(1 << 30) * 64))
+    assert st == 0 and big <= 2 * small  # capped number of partial sums
+    assert ws_status(desc(), 1)[0] == 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(N=0), 1), (dict(B=0), 1), (dict(H=-1), 1),
+    (dict(d=48, in_sn=48, out_sn=48, in_sh=4800, out_sh=4800, in_sb=9600, out_sb=9600), 2),
+    (dict(d=256, in_sn=256, out_sn=256, in_sh=25600, out_sh=25600, in_sb=51200, out_sb=51200), 2),
+    (dict(in_dtype=7), 1), (dict(out_dtype=-1), 1), (dict(feature_map=3), 2),
+    (dict(flags=1), 1), (dict(in_sn=60), 1), (dict(in_sn=68), 1), (dict(out_sh=-64), 1),
+    (dict(in_sb=12802), 1),
+])
+def test_bad_descriptors_are_rejected(kw, status):
+    assert ws_status(desc(**kw))[0] == status
+
+
+def test_forward_rejects_bad_pointers_before_gpu_work():
+    L = la.lib()
+    d = desc()
+    ws = ctypes.c_size_t(0)
+    L.la_workspace_size(ctypes.byref(d), 0, ctypes.byref(ws))
+    fake = 1 << 20  # never dereferenced: every case fails validation first
+    args = [fake, fake, fake, fake]
+    assert L.la_forward(ctypes.byref(d), None, fake, fake, fake, None, None, fake, ws.value, None) == 1
+    assert L.la_forward(ctypes.byref(d), fake + 2, fake, fake, fake, None, None, fake, ws.value, None) == 1
+    assert L.la_forward(ctypes.byref(d), *args, None, None, fake + 16, ws.value, None) == 1  # ws alignment
+    assert L.la_forward(ctypes.byref(d), *args, None, None, fake, ws.value - 1, None) == 3
+    assert L.la_forward(ctypes.byref(d), *args, fake + 4, None, fake, ws.value, None) == 1
+    assert L.la_backward(ctypes.byref(d), *args[:3], None, fake, fake, fake, fake, fake, fake,
+                         ws.value, None) == 1
+    assert L.la_forward(None, *args, None, None, fake, ws.value, None) == 1
+
+
+def test_generator_rejects_bad_arguments():
+    G = B.gen_lib()
+    spec = B.GenSpec(1, 0, 0, 0.0, 1.0, 0, 0, 0, 1.0)
+    fake = 1 << 20
+    assert G.la_gen_fill(None, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
+    assert G.la_gen_fill(fake + 2, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
+    assert G.la_gen_fill(fake, 2, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
+    grid = B.GenSpec(1, 0, 0, 0.0, 1.0, 2, 2, 3, 1.0)  # 12 tokens != N
+    assert G.la_gen_fill(fake, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(grid), None) == 1
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/liblinattn.so")
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError):
+        B.lib()

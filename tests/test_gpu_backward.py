@@ -1,0 +1,179 @@
+"""Backward parity: la_backward and the autograd.Function against the FP64
+oracle's gradients (which are themselves pinned to finite differences and
+to autograd of the quadratic form).  Tolerances, normwise per (b, h):
+bf16 2e-2, fp32 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_16590_amd as la
+from gpu_util import TOL, as64, make_inputs, max_rel, normwise, require_gpu, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_grads(q, k, v, g, grad_dtype=None):
+    dev = require_gpu()
+    tq, tk, tv, tg = (to_device(x, dev) for x in (q, k, v, g))
+    _, S, z = la.forward(tq, tk, tv, return_summary=True)
+    res = la.backward(tq, tk, tv, S, z, tg, grad_dtype=grad_dtype)
+    torch.cuda.synchronize()
+    return res
+
+
+def check(shape, dtype, seed, grad_dtype=None, tol=None):
+    q, k, v, g = make_inputs(shape, dtype, seed, streams=(0, 1, 2, 3))
+    print("case", shape, dtype, seed, grad_dtype, flush=True)
+    dq, dk, dv = gpu_grads(q, k, v, g, grad_dtype)
+    rq, rk, rv = oracle.backward(q, k, v, g)
+    tol = tol or TOL[dtype]
+    if shape[2] == 1:
+        # one token: O = v_1 whatever q and k are, so dQ = dK = 0 exactly;
+        # the computed values are differences of terms of size |G||v|
+        scale = np.abs(g.astype(np.float64) if g.dtype != np.uint16 else as64(g)).max() * \
+            np.abs(v.astype(np.float64) if v.dtype != np.uint16 else as64(v)).max()
+        assert np.abs(as64(dq)).max() < tol * scale and np.abs(as64(dk)).max() < tol * scale
+        err = normwise(as64(dv), rv)
+        assert err < tol, ("dv", err)
+        return {"dv": err}
+    errs = {name: normwise(as64(x), r) for name, x, r in (("dq", dq, rq), ("dk", dk, rk), ("dv", dv, rv))}
+    print("  normwise", errs, flush=True)
+    for name, e in errs.items():
+        assert e < tol, (name, e)
+    return errs
+
+
+@pytest.mark.parametrize("d", [16, 32, 64, 128])
+@pytest.mark.parametrize("dtype", ["bf16", "fp32"])
+@pytest.mark.parametrize("N", [1, 5, 33, 1000, 4097])
+def test_ragged_and_all_head_dims(N, d, dtype):
+    check((2, 2, N, d), dtype, seed=31 + N + d)
+
+
+@pytest.mark.parametrize("d", [64, 128])
+def test_many_partials_and_tail(d):
+    check((1, 2, 2 * 8192 * (2 if d == 128 else 1) + 45, d), "bf16", seed=32)
+
+
+def test_bf16_inputs_fp32_gradients():
+    errs = check((1, 2, 3000, 64), "bf16", seed=33, grad_dtype=torch.float32)
+    assert max(errs.values()) < 5e-3
+
+
+def test_autograd_function_matches_oracle():
+    dev = require_gpu()
+    q, k, v, g = make_inputs((2, 3, 2500, 64), "bf16", 34, streams=(0, 1, 2, 3))
+    tq, tk, tv = (to_device(x, dev).requires_grad_(True) for x in (q, k, v))
+    o = la.linear_attention(tq, tk, tv)
+    (o.float() * to_device(g, dev).float()).sum().backward()
+    torch.cuda.synchronize()
+    rq, rk, rv = oracle.backward(q, k, v, g)
+    assert normwise(as64(o), oracle.forward(q, k, v)) < TOL["bf16"]
+    for x, r in ((tq.grad, rq), (tk.grad, rk), (tv.grad, rv)):
+        assert normwise(as64(x), r) < TOL["bf16"]
+
+
+def test_autograd_with_strided_inputs_and_fp32():
+    dev = require_gpu()
+    B, N, H, d = 1, 700, 2, 32
+    q, k, v, g = make_inputs((B, N, H, d), "fp32", 35, streams=(0, 1, 2, 3))
+    tq, tk, tv = (to_device(x, dev).permute(0, 2, 1, 3).detach().requires_grad_(True)
+                  for x in (q, k, v))
+    tg = to_device(g, dev).permute(0, 2, 1, 3)
+    o = la.linear_attention(tq, tk, tv)
+    o.backward(tg)
+    torch.cuda.synchronize()
+    perm = lambda a: np.ascontiguousarray(a.transpose(0, 2, 1, 3))
+    rq, rk, rv = oracle.backward(perm(q), perm(k), perm(v), perm(g))
+    for x, r in ((tq.grad, rq), (tk.grad, rk), (tv.grad, rv)):
+        assert normwise(as64(x.contiguous()), r) < TOL["fp32"]
+
+
+def test_value_gradient_column_sums_equal_upstream_sums():
+    q, k, v, g = make_inputs((1, 2, 30000, 64), "fp32", 36, streams=(0, 1, 2, 3))
+    dq, dk, dv = gpu_grads(q, k, v, g)
+    lhs = as64(dv).sum(2)
+    rhs = g.astype(np.float64).sum(2)
+    assert normwise(lhs[..., None], rhs[..., None]) < 1e-5
+
+
+def test_constant_values_give_vanishing_query_and_key_gradients():
+    from paper_2604_16590_amd import inputs
+    shape = (1, 1, 5000, 64)
+    q, k, _, g = make_inputs(shape, "fp32", 37, streams=(0, 1, 2, 3))
+    row = inputs.generate(inputs.GenSpec(seed=37, stream=9), (1, 1, 1, 64), "fp32")
+    v = np.ascontiguousarray(np.broadcast_to(row, shape))
+    dq, dk, dv = gpu_grads(q, k, v, g)
+    # exact gradients are 0; compare with the scale of the terms that cancel
+    scale_q = np.abs(as64(dv)).max() * np.abs(v).max()
+    assert np.abs(as64(dq)).max() < 1e-4 * max(scale_q, 1e-30) * 10
+    assert np.abs(as64(dk)).max() < 1e-4 * max(scale_q, 1e-30) * 10
+
+
+def test_backward_bitwise_deterministic():
+    dev = require_gpu()
+    xs = [to_device(x, dev) for x in make_inputs((1, 4, 40000, 128), "bf16", 38, streams=(0, 1, 2, 3))]
+    _, S, z = la.forward(*xs[:3], return_summary=True)
+    a = la.backward(*xs[:3], S, z, xs[3])
+    b = la.backward(*xs[:3], S, z, xs[3])
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_config4_full_size_sampled_heads():
+    # N = 262,144 (T64 x 64 x 64), B2 H16 d64, bf16, upstream gradient N(0,1);
+    # the oracle recomputes two whole heads.
+    dev = require_gpu()
+    B, H, N, d = 2, 16, 262144, 64
+    xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device=dev) for _ in range(4)]
+    for sid, x in enumerate(xs):
+        la.gen_fill(x, seed=1003, stream_id=sid)
+    q, k, v, g = (x.detach().requires_grad_(i < 3) for i, x in enumerate(xs))
+    o = la.linear_attention(q, k, v)
+    o.backward(g)
+    torch.cuda.synchronize()
+    for b, h in ((0, 0), (1, 15)):
+        host = [to_host(x[b:b + 1, h:h + 1]) for x in xs]
+        rq, rk, rv = oracle.backward(*host)
+        for name, x, r in (("dq", q.grad, rq), ("dk", k.grad, rk), ("dv", v.grad, rv)):
+            err = normwise(as64(x[b:b + 1, h:h + 1]), r)
+            print("config4 head", (b, h), name, err, flush=True)
+            assert err < TOL["bf16"]
+    # at any size: sum_j dV_j = sum_i G_i per (b, h, feature)
+    lhs = v.grad.double().sum(2)
+    rhs = g.double().sum(2)
+    rel = ((lhs - rhs).norm(dim=-1) / rhs.norm(dim=-1)).max().item()
+    print("config4 column-sum identity", rel)
+    assert rel < TOL["bf16"]
+
+
+def test_config3_long_context_fwd_bwd_sampled_rows():
+    # 2,097,152 tokens, B1 H8 d128, bf16: one head checked against the
+    # oracle (exact S, z, dS, dz over all tokens; dQ/dK/dV on sampled rows).
+    dev = require_gpu()
+    B, H, N, d = 1, 8, 2097152, 128
+    xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device=dev) for _ in range(4)]
+    for sid, x in enumerate(xs):
+        la.gen_fill(x, seed=1002, stream_id=sid, std=(0.5 ** 0.5 if sid < 3 else 1.0))
+    _, S, z = la.forward(*xs[:3], return_summary=True)
+    dq, dk, dv = la.backward(*xs[:3], S, z, xs[3])
+    torch.cuda.synchronize()
+    h = 5
+    hq, hk, hv, hg = (to_host(x[:, h:h + 1]) for x in xs)
+    S_ref, z_ref = oracle.summary(hk, hv)
+    _, dS_ref, dz_ref = oracle.backward_query(hq, hg, S_ref, z_ref, want_dq=False)
+    rows = np.sort(np.random.default_rng(5).choice(N, 2048, replace=False))
+    sel = lambda a: np.ascontiguousarray(a[:, :, rows])
+    rdq, _, _ = oracle.backward_query(sel(hq), sel(hg), S_ref, z_ref)
+    rdk, rdv = oracle.backward_key(sel(hk), sel(hv), dS_ref, dz_ref)
+    idx = torch.from_numpy(rows).to(dev)
+    for name, x, r in (("dq", dq, rdq), ("dk", dk, rdk), ("dv", dv, rdv)):
+        err = normwise(as64(x[:, h:h + 1, idx]), r)
+        print("config3 bwd", name, err, max_rel(as64(x[:, h:h + 1, idx]), r), flush=True)
+        assert err < TOL["bf16"]
+    lhs = dv.double().sum(2)
+    rhs = xs[3].double().sum(2)
+    assert ((lhs - rhs).norm(dim=-1) / rhs.norm(dim=-1)).max().item() < TOL["bf16"]
