@@ -1,0 +1,309 @@
+#!/usr/bin/env python
+"""Throughput of kernelised linear global attention on one MI355X.
+
+Workload (the long-context single-GPU shard): T = 256 frames x 64 x 128
+patches = 2,097,152 tokens, batch 1, 8 heads, d = 128, bf16 Q/K/V drawn
+N(0, variance 0.5) and an upstream gradient N(0, 1), all synthetic and
+generated in HBM before timing.  One step = forward (summary, FP64
+combine, apply) + backward (query pass, dS reduction, FP64 combine, key
+pass): every step of the hot path.  The same step in fp32, the forward
+alone, per-kernel HIP-event timings and the FP64 CPU oracle on a bounded
+sample are reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BF16_PEAK_TFLOPS = 2500.0      # dense MFMA bf16
+FP32_PEAK_TFLOPS = 157.3       # fp32 (matrix and vector)
+
+METRIC = "attn tokens/s fwd & fwd+bwd at 2M tok, BF16 vs FP32; serve p50/p99 ms"
+WORKLOAD = dict(B=1, H=8, N=2097152, d=128, grid=(256, 64, 128), std_qkv=0.5 ** 0.5)
+
+# Tensor passes over HBM per launch of each kernel (each pass = B*H*N*d
+# elements): what the kernel has to read and write for its part of the
+# method, not what it happens to fetch.
+KERNEL_PASSES = {
+    "summary_fwd": 2,   # read K, V
+    "apply": 2,         # read Q, write O
+    "bwd_query": 3,     # read Q, dO; write dQ
+    "summary_bwd": 2,   # read Q, dO
+    "bwd_key": 4,       # read K, V; write dK, dV
+}
+# matrix-core FLOPs per launch, in units of 2*B*H*N*d^2
+KERNEL_MMA = {"summary_fwd": 1, "apply": 2, "bwd_query": 2, "summary_bwd": 1, "bwd_key": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--cpu-tokens", type=int, default=65536,
+                    help="tokens per head of the oracle sample (8 heads, d = 128)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(dtype, with_grad=True):
+    import torch
+    import paper_2604_16590_amd as la
+    w = WORKLOAD
+    shape = (w["B"], w["H"], w["N"], w["d"])
+    xs = []
+    for sid in range(4 if with_grad else 3):
+        x = torch.empty(shape, dtype=dtype, device="cuda:0")
+        la.gen_fill(x, seed=1002, stream_id=sid, std=w["std_qkv"] if sid < 3 else 1.0)
+        xs.append(x)
+    torch.cuda.synchronize()
+    return xs
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_table(stats, steps, elems, esize):
+    out = {}
+    for name, (launches, ms) in stats.items():
+        avg = ms / max(launches, 1)
+        row = {"launches_per_step": launches / steps, "avg_ms": round(avg, 4)}
+        if name in KERNEL_PASSES:
+            nbytes = KERNEL_PASSES[name] * elems * esize
+            row["alg_GB"] = round(nbytes / 1e9, 3)
+            row["GB_s"] = round(nbytes / (avg * 1e-3) / 1e9, 1)
+        out[name] = row
+    return out
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2604_16590_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters_long_context_bf16.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_tokens):
+    """The FP64 oracle (as it stands) on a bounded sample of the workload:
+    B1 H8 n_tokens d128 bf16, forward + backward; also the GPU's normwise
+    error on that same sample."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2604_16590_amd as la
+    w = WORKLOAD
+    shape = (1, w["H"], n_tokens, w["d"])
+    xs = []
+    for sid in range(4):
+        x = torch.empty(shape, dtype=torch.bfloat16, device="cuda:0")
+        la.gen_fill(x, seed=77, stream_id=sid, std=w["std_qkv"] if sid < 3 else 1.0)
+        xs.append(x)
+    torch.cuda.synchronize()
+    host = [x.cpu().view(torch.int16).numpy().view(np.uint16) for x in xs]
+    oracle._load()
+    t0 = time.perf_counter()
+    o_ref = oracle.forward(*host[:3])
+    dq_r, dk_r, dv_r = oracle.backward(*host)
+    dt = time.perf_counter() - t0
+    plan = la.Plan(*xs[:3], dout=xs[3])
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+
+    def err(t, ref):
+        a = t.float().cpu().numpy().astype(np.float64)
+        num = np.linalg.norm((a - ref).reshape(shape[1], -1), axis=1)
+        return float((num / np.linalg.norm(ref.reshape(shape[1], -1), axis=1)).max())
+
+    errors = {"o": err(plan.o, o_ref), "dq": err(plan.dq, dq_r), "dk": err(plan.dk, dk_r),
+              "dv": err(plan.dv, dv_r)}
+    return {
+        "value": round(n_tokens / dt, 1), "unit": "tokens/s", "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": "fwd+bwd, B1 H8 N%d d128 bf16 N(0,0.5) inputs, FP64 oracle, %.1f s" % (n_tokens, dt),
+    }, errors
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(token shards would exchange one (S, z) sum per pass); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_16590_amd as la
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 1 GiB x3")
+        return
+
+    w = WORKLOAD
+    elems = w["B"] * w["H"] * w["N"] * w["d"]
+    tokens = w["B"] * w["N"]
+
+    # ---- bf16: the timed step (forward + backward) ----
+    log("generating bf16 inputs")
+    xs = make_inputs(torch.bfloat16)
+    plan = la.Plan(*xs[:3], dout=xs[3])
+
+    def step():
+        plan.forward()
+        plan.backward()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    la.profile_enable(True)
+    t_step = time_steps(step, args.steps, 0)
+    stats = la.profile_read()
+    la.profile_enable(False)
+    log("bf16 fwd+bwd %.3f ms/step" % (t_step * 1e3))
+    t_fwd = time_steps(plan.forward, args.steps, 1)
+    log("bf16 fwd %.3f ms" % (t_fwd * 1e3))
+
+    kernels = kernel_table(stats, args.steps, elems, 2)
+    timed = {k: v for k, v in kernels.items() if k in KERNEL_PASSES}
+    dominant = max(timed, key=lambda k: timed[k]["avg_ms"] * timed[k]["launches_per_step"])
+    dk = kernels[dominant]
+    achieved = dk["GB_s"]
+    traffic = traffic_for(dominant)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+    mma_flops = sum(KERNEL_MMA[k] * 2 * elems * w["d"] for k in KERNEL_MMA)
+    step_bytes = sum(KERNEL_PASSES.values()) * elems * 2
+    del plan, xs
+    torch.cuda.empty_cache()
+
+    # ---- fp32: the same step in plain fp32 ----
+    fp32 = None
+    if not args.no_fp32:
+        log("generating fp32 inputs")
+        xs = make_inputs(torch.float32)
+        p32 = la.Plan(*xs[:3], dout=xs[3])
+
+        def step32():
+            p32.forward()
+            p32.backward()
+
+        n32 = max(2, args.steps // 4)
+        t32 = time_steps(step32, n32, 1)
+        t32f = time_steps(p32.forward, n32, 1)
+        fp32 = {"fwd_bwd_tokens_per_s": round(tokens / t32, 1), "fwd_tokens_per_s": round(tokens / t32f, 1),
+                "ms_per_step": round(t32 * 1e3, 3), "fwd_ms": round(t32f * 1e3, 3),
+                "mma_frac_of_fp32_peak": round(mma_flops / t32 / 1e12 / FP32_PEAK_TFLOPS, 4)}
+        log("fp32 fwd+bwd %.3f ms" % (t32 * 1e3))
+        del p32, xs
+        torch.cuda.empty_cache()
+
+    # ---- serving (ensemble-member requests, continuous batching) ----
+    serve = None
+    if not args.no_serve:
+        from paper_2604_16590_amd import serve as serve_mod
+        log("serving: Poisson stream of ensemble requests")
+        try:
+            serve = serve_mod.bench_summary()
+        except Exception as ex:  # reported, not hidden: the line says what failed
+            serve = {"error": "%s: %s" % (type(ex).__name__, ex)}
+        torch.cuda.empty_cache()
+
+    # ---- oracle on the host cores, plus the GPU's error on that sample ----
+    cpu = None
+    errors = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        cpu, errors = cpu_baseline(args.cpu_tokens)
+
+    result = {
+        "metric": METRIC,
+        "value": round(tokens / t_step, 1),
+        "unit": "tokens/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "long-context shard fwd+bwd: T256 x 64 x 128 = 2,097,152 tokens, "
+                               "B1 H8 d128, bf16 N(0,0.5) Q/K/V, upstream grad N(0,1)",
+                   "global_batch": w["B"], "seq_len": w["N"], "heads": w["H"], "head_dim": w["d"],
+                   "parallelism": "single GPU"},
+        "fwd_tokens_per_s": round(tokens / t_fwd, 1),
+        "fwd_ms": round(t_fwd * 1e3, 4),
+        "step_alg_GB": round(step_bytes / 1e9, 3),
+        "step_GB_s": round(step_bytes / t_step / 1e9, 1),
+        "step_mma_TFLOP_s": round(mma_flops / t_step / 1e12, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+        "fp32": fp32,
+        "serve": serve,
+        "cpu_baseline": cpu,
+        "errors_vs_oracle_on_sample": errors,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,97 @@ la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,
                       const void* dout, void* dq, void* dk, void* dv, void* ws,
                       size_t ws_bytes, la_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop for ensemble members.
+ *
+ * The paper generates large posterior ensembles, one member per sampler,
+ * each running the denoiser (and its attention) at every diffusion step
+ * (Sec. V, large-scale ensemble generation, 80 diffusion steps).  Requests
+ * here are attention calls of one ensemble batch (B members sharing N, H,
+ * d).  The server:
+ *  - queues requests FIFO and splits each into member slices;
+ *  - admits the next slice of the oldest request when a slot is free and
+ *    the slice's device memory fits the free HBM budget (head-of-line
+ *    order: a request never overtakes an older one);
+ *  - runs each slice (optional input generation, summary, combine, apply)
+ *    on one of its HIP streams, so slices of different requests overlap on
+ *    the GPU;
+ *  - keeps each request's FP64 summary S and normaliser z (and, for
+ *    generated inputs, the output O) in device memory until the client
+ *    releases the request.
+ * Member results do not depend on how a request is sliced or what else
+ * runs: tiling depends only on (N, d, dtype), so a request computes the
+ * same bits alone and in a mix.
+ * ------------------------------------------------------------------------ */
+typedef struct la_server la_server;
+
+typedef struct {
+  int32_t device;                 /* HIP device ordinal */
+  uint64_t hbm_budget_bytes;      /* device memory the server may hold at once */
+  int32_t max_slots;              /* slices in flight at once, >= 1 */
+  int32_t n_streams;              /* HIP streams the slices rotate over, >= 1 */
+  int32_t max_members_per_slice;  /* 0 = as many as fit */
+  int32_t fake_executor;          /* test hook: 1 = no GPU work, slices finish
+                                     fake_slice_ns after launch (budget, FIFO
+                                     and slicing logic only) */
+  int64_t fake_slice_ns;
+} la_server_config;
+
+typedef struct {
+  la_attn_desc desc;     /* B = members; H, N, d, dtypes; strides as for la_forward */
+  const void* q;         /* caller-owned device inputs and output, kept alive by */
+  const void* k;         /* the caller until the request is DONE or FAILED;      */
+  const void* v;         /* all NULL when generate = 1                           */
+  void* o;
+  int32_t generate;      /* 1: the server allocates Q, K, V, O in its budget and
+                            fills Q, K, V with the seeded generator (streams 0, 1,
+                            2 of gen_seed, N(0, gen_std^2)); desc strides are then
+                            ignored ([B,H,N,d] contiguous) */
+  uint64_t gen_seed;
+  double gen_std;
+  uint64_t t_arrival_ns; /* scheduled arrival on CLOCK_MONOTONIC; 0 = at submit */
+} la_request;
+
+enum { LA_REQ_QUEUED = 0, LA_REQ_RUNNING = 1, LA_REQ_DONE = 2, LA_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;          /* LA_REQ_* */
+  la_status error;        /* why it FAILED */
+  uint64_t t_arrival_ns, t_admit_ns, t_done_ns;  /* CLOCK_MONOTONIC */
+  int32_t slices;         /* member slices the request was split into */
+  void* o;                /* output (server-owned for generated requests) */
+  double* s;              /* [B][H][d][d] FP64 summary, server-owned */
+  double* z;              /* [B][H][d]    FP64 normaliser, server-owned */
+} la_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed, rejected;
+  int64_t queued, in_flight_slices;
+  uint64_t bytes_in_use, peak_bytes_in_use, budget_bytes;
+} la_serve_counters;
+
+/* Create a server (allocates its budget on `device` and starts its
+ * scheduler thread).  Errors: LA_ERR_INVALID_ARG, LA_ERR_OOM, LA_ERR_HIP. */
+la_status la_serve_create(const la_server_config* cfg, la_server** out);
+/* Stop accepting work, cancel queued requests (FAILED, LA_ERR_SHUTDOWN),
+ * wait for slices in flight, free everything. */
+la_status la_serve_destroy(la_server* srv);
+/* Non-blocking.  LA_ERR_OOM when even a one-member slice cannot fit the
+ * budget; LA_ERR_SHUTDOWN during destroy; argument errors as la_forward. */
+la_status la_serve_submit(la_server* srv, const la_request* req, uint64_t* id);
+/* Non-blocking snapshot.  LA_ERR_NOT_FOUND for unknown or released ids. */
+la_status la_serve_poll(la_server* srv, uint64_t id, la_result* out);
+/* Free a finished request's device memory (S, z, generated O).
+ * LA_ERR_BUSY while it is queued or running. */
+la_status la_serve_release(la_server* srv, uint64_t id);
+la_status la_serve_stats(la_server* srv, la_serve_counters* out);
+/* Test hook: slice `slice` (0-based) of request `id` fails instead of
+ * running, as a device-side failure would. */
+la_status la_serve_debug_fail_slice(la_server* srv, uint64_t id, int32_t slice);
+/* Test hook: while paused (1) the scheduler admits nothing; slices already
+ * in flight still finish.  0 resumes. */
+la_status la_serve_debug_pause(la_server* srv, int32_t paused);
+
 /*
  * Opt-in kernel timing.  la_profile_enable(1) clears earlier records and
  * makes every subsequent kernel launch of this library record a pair of

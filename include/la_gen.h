@@ -8,7 +8,8 @@
  * paper_2604_16590_amd/inputs.py implements the same definition:
  *
  *  - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).  Element e of the
- *    logical [B,H,N,d] tensor (row-major flat index) uses counter
+ *    logical [b_offset + B, H, N, d] tensor (row-major flat index; the
+ *    filled tensor is its batches b_offset .. b_offset + B - 1) uses counter
  *    (lo32(e>>1), hi32(e>>1), stream, 0) and key (lo32(seed), hi32(seed)).
  *  - u1 = ((x0 >> 9) + 0.5) * 2^-23, u2 = (x1 >> 8) * 2^-24; Box-Muller in
  *    FP64: r = sqrt(-2 ln u1), t = 2 pi u2; even e takes r cos t, odd e
@@ -42,6 +43,7 @@ typedef struct {
   double mean, std;
   int32_t grid_T, grid_lat, grid_lon; /* grid_T = 0: no structure */
   double amplitude;
+  int64_t b_offset;  /* first logical batch index of the filled tensor */
 } la_gen_spec;
 
 /*

@@ -46,7 +46,7 @@ class GenSpec(ctypes.Structure):
                 ("tensor_id", ctypes.c_int32), ("mean", ctypes.c_double),
                 ("std", ctypes.c_double), ("grid_T", ctypes.c_int32),
                 ("grid_lat", ctypes.c_int32), ("grid_lon", ctypes.c_int32),
-                ("amplitude", ctypes.c_double)]
+                ("amplitude", ctypes.c_double), ("b_offset", ctypes.c_int64)]
 
 
 _lib = None
@@ -186,13 +186,13 @@ def backward(q, k, v, S, z, dout, grad_dtype=None):
 
 
 def gen_fill(x: torch.Tensor, seed: int, stream_id: int, mean=0.0, std=1.0, grid=None,
-             amplitude=1.0, tensor_id=None):
+             amplitude=1.0, tensor_id=None, b_offset=0):
     """Fill a [B,H,N,d] GPU tensor with the seeded synthetic inputs."""
     B, H, N, d = x.shape
     sb, sh, sn = _strides(x)
     T, nlat, nlon = grid if grid else (0, 0, 0)
     spec = GenSpec(seed, stream_id, stream_id if tensor_id is None else tensor_id,
-                   mean, std, T, nlat, nlon, amplitude)
+                   mean, std, T, nlat, nlon, amplitude, b_offset)
     rc = gen_lib().la_gen_fill(x.data_ptr(), _dtype_code(x.dtype), B, H, N, d, sb, sh, sn,
                                ctypes.byref(spec), _stream(x.device))
     if rc != 0:
@@ -224,3 +224,65 @@ class LinearAttention(torch.autograd.Function):
 
 def linear_attention(q, k, v):
     return LinearAttention.apply(q, k, v)
+
+
+def profile_enable(on: bool):
+    _check("la_profile_enable", lib().la_profile_enable(1 if on else 0))
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+def profile_read():
+    """{kernel name: (launches, total milliseconds)} since profile_enable(True)."""
+    L = lib()
+    L.la_profile_read.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.la_profile_read.restype = ctypes.c_int
+    cap = 64
+    arr = (KernelStat * cap)()
+    n = ctypes.c_int32(0)
+    _check("la_profile_read", L.la_profile_read(arr, cap, ctypes.byref(n)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, cap))}
+
+
+class Plan:
+    """Preallocated forward + backward of one problem shape: outputs, the
+    FP64 summary and both workspaces are allocated once, so repeated calls
+    only enqueue kernels."""
+
+    def __init__(self, q, k, v, dout=None, out_dtype=None):
+        _same_layout(q, k, "k")
+        _same_layout(q, v, "v")
+        B, H, N, d = q.shape
+        dev = q.device
+        self.q, self.k, self.v, self.dout = q, k, v, dout
+        od = out_dtype or q.dtype
+        self.o = torch.empty((B, H, N, d), dtype=od, device=dev)
+        self.S = torch.empty((B, H, d, d), dtype=torch.float64, device=dev)
+        self.z = torch.empty((B, H, d), dtype=torch.float64, device=dev)
+        self.desc = make_desc(q, self.o)
+        self.ws_f = _workspace(workspace_size(self.desc, 0), dev)
+        if dout is not None:
+            _same_layout(q, dout, "dout")
+            self.dq = torch.empty_like(self.o)
+            self.dk = torch.empty_like(self.o)
+            self.dv = torch.empty_like(self.o)
+            self.ws_b = _workspace(workspace_size(self.desc, 1), dev)
+        self.stream = _stream(dev)
+        self._d = ctypes.byref(self.desc)
+
+    def forward(self):
+        _check("la_forward", lib().la_forward(
+            self._d, self.q.data_ptr(), self.k.data_ptr(), self.v.data_ptr(),
+            self.o.data_ptr(), self.S.data_ptr(), self.z.data_ptr(), self.ws_f.data_ptr(),
+            self.ws_f.numel(), self.stream))
+
+    def backward(self):
+        _check("la_backward", lib().la_backward(
+            self._d, self.q.data_ptr(), self.k.data_ptr(), self.v.data_ptr(),
+            self.S.data_ptr(), self.z.data_ptr(), self.dout.data_ptr(), self.dq.data_ptr(),
+            self.dk.data_ptr(), self.dv.data_ptr(), self.ws_b.data_ptr(), self.ws_b.numel(),
+            self.stream))

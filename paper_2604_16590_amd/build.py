@@ -21,9 +21,12 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result"]
 
+# liblagen.so first: liblinattn.so links it (the serving loop generates
+# inputs for requests that ask for them).
 LIBS = {
-    "liblinattn.so": ["la_api.cpp", "la_forward.hip", "la_backward.hip", "la_serve.cpp", "la_profile.cpp"],
     "liblagen.so": ["gen.hip"],
+    "liblinattn.so": ["la_api.cpp", "la_forward.hip", "la_backward.hip", "la_serve.cpp",
+                      "la_profile.cpp"],
 }
 
 
@@ -49,7 +52,7 @@ def build(verbose: bool = False) -> dict:
         tmp = path + ".tmp%d" % os.getpid()
         cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + present
         if lib == "liblinattn.so":
-            cmd += ["-lpthread"]
+            cmd += ["-L" + HERE, "-llagen", "-Wl,-rpath,$ORIGIN", "-lpthread"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed for %s:\n%s" % (lib, r.stderr))

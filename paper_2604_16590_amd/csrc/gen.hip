@@ -41,6 +41,7 @@ struct GenArgs {
   double mean, std;
   int grid_T, grid_lat, grid_lon;
   double amplitude;
+  int64_t b_offset;
 };
 
 __device__ __forceinline__ double structure(const GenArgs& a, int64_t h, int64_t n, int64_t c) {
@@ -60,7 +61,9 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const double kTwoPi = 6.28318530717958647692;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += stride) {
-    uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), a.stream, 0u};
+    // logical pair index in the [b_offset + B, H, N, d] tensor
+    const int64_t lp = p + a.b_offset * a.H * a.N * a.d / 2;
+    uint32_t c[4] = {(uint32_t)lp, (uint32_t)((uint64_t)lp >> 32), a.stream, 0u};
     philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
     const double u1 = ((double)(c[0] >> 9) + 0.5) * 0x1p-23;
     const double u2 = (double)(c[1] >> 8) * 0x1p-24;
@@ -109,6 +112,8 @@ extern "C" int32_t la_gen_fill(void* dst, int32_t dtype, int64_t B, int64_t H, i
   a.mean = spec->mean; a.std = spec->std;
   a.grid_T = spec->grid_T; a.grid_lat = spec->grid_lat; a.grid_lon = spec->grid_lon;
   a.amplitude = spec->amplitude;
+  a.b_offset = spec->b_offset;
+  if (a.b_offset < 0) return 1;
   const int64_t pairs = B * H * N * d / 2;
   int64_t blocks = (pairs + 255) / 256;
   if (blocks > 65536) blocks = 65536;

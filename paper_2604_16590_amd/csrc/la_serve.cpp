@@ -1,0 +1,539 @@
+// la_serve.cpp -- continuous-batching request loop (include/la.h, la_serve_*).
+//
+// One scheduler thread per server.  Each tick it retires finished slices,
+// then admits slices of the oldest request while a slot is free and the
+// slice's device memory fits the free part of the HBM budget.  A slice is a
+// contiguous run of the request's members (ensemble members are independent
+// problems with the same N, H, d), so the members of a large request can
+// run as memory frees up while other requests' slices overlap on the
+// device.  The budget is one device allocation carved by a first-fit
+// allocator, so admission never calls hipMalloc.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/la.h"
+#include "../../include/la_gen.h"
+#include "la_kernels.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over [0, size) with coalescing of freed blocks.
+class Arena {
+ public:
+  void init(size_t size) {
+    size_ = size;
+    free_.clear();
+    if (size) free_[0] = size;
+    in_use_ = peak_ = 0;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = align_up(n ? n : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, start = it->first + n;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        in_use_ += n;
+        peak_ = std::max(peak_, in_use_);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align_up(n ? n : 1);
+    in_use_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+  size_t size() const { return size_; }
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  size_t size_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Slice {
+  uint64_t req;
+  int index;
+  int64_t b0, m;       // members [b0, b0 + m)
+  size_t off, bytes;   // transient block: generated inputs + workspace
+  int stream;
+  hipEvent_t done;
+  uint64_t t_fake_done;
+  bool fail;
+};
+
+struct Request {
+  la_request spec;
+  int32_t state = LA_REQ_QUEUED;
+  la_status error = LA_OK;
+  uint64_t t_arrival = 0, t_admit = 0, t_done = 0;
+  int64_t next_member = 0;
+  int slices_started = 0, slices_done = 0;
+  bool failed = false;
+  size_t keep_off = 0, keep_bytes = 0;  // S, z (+ O when generated)
+  bool keep_held = false;
+  void* o = nullptr;
+  double* s = nullptr;
+  double* z = nullptr;
+};
+
+int64_t esize(int32_t dt) { return dt == LA_BF16 ? 2 : 4; }
+
+size_t member_tensor_bytes(const la_attn_desc& d, int32_t dt) {
+  return (size_t)(d.H * d.N * d.d * esize(dt));
+}
+
+}  // namespace
+
+struct la_server {
+  la_server_config cfg{};
+  char* base = nullptr;  // device memory of the budget (null with the fake executor)
+  Arena arena;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;  // pool
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> fifo;
+  std::unordered_map<uint64_t, Request> reqs;
+  std::vector<Slice> inflight;
+  std::set<std::pair<uint64_t, int>> fail_at;
+  std::thread th;
+  bool stopping = false;
+  bool paused = false;
+  uint64_t next_id = 1;
+  uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_rejected = 0;
+  int next_stream = 0;
+};
+
+namespace {
+
+// Transient bytes of a slice of m members: generated Q, K, V plus the
+// forward workspace.  Kept bytes of a request: S, z and a generated O.
+size_t slice_bytes(const la_request& r, int64_t m) {
+  la_attn_desc d = r.desc;
+  d.B = m;
+  if (r.generate) {
+    d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh; d.in_sn = d.d;
+    d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh; d.out_sn = d.d;
+  }
+  size_t ws = 0;
+  la_workspace_size(&d, 0, &ws);
+  size_t b = align_up(ws);
+  if (r.generate) b += 3 * align_up(member_tensor_bytes(d, d.in_dtype) * (size_t)m);
+  return b;
+}
+
+size_t keep_bytes(const la_request& r) {
+  const la_attn_desc& d = r.desc;
+  size_t b = align_up((size_t)(d.B * d.H * d.d * d.d) * 8) + align_up((size_t)(d.B * d.H * d.d) * 8);
+  if (r.generate) b += align_up(member_tensor_bytes(d, d.out_dtype) * (size_t)d.B);
+  return b;
+}
+
+hipEvent_t take_event(la_server* s) {
+  if (!s->events.empty()) {
+    hipEvent_t e = s->events.back();
+    s->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (s->cfg.fake_executor) return e;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue one slice on its stream (called with the lock held).
+la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
+  if (sl.fail) return LA_ERR_HIP;  // injected device failure
+  if (s->cfg.fake_executor) {
+    sl.t_fake_done = now_ns() + (uint64_t)s->cfg.fake_slice_ns;
+    return LA_OK;
+  }
+  const la_request& r = rq.spec;
+  la_attn_desc d = r.desc;
+  d.B = sl.m;
+  hipStream_t st = s->streams[sl.stream];
+  char* blk = s->base + sl.off;
+  const void *q, *k, *v;
+  void* o;
+  if (r.generate) {
+    d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh; d.in_sn = d.d;
+    d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh; d.out_sn = d.d;
+    const size_t tb = align_up(member_tensor_bytes(d, d.in_dtype) * (size_t)sl.m);
+    char* gq = blk;
+    char* gk = blk + tb;
+    char* gv = blk + 2 * tb;
+    char* bufs[3] = {gq, gk, gv};
+    for (int t = 0; t < 3; ++t) {
+      la_gen_spec g{};
+      g.seed = r.gen_seed;
+      g.stream = (uint32_t)t;
+      g.tensor_id = t;
+      g.mean = 0.0;
+      g.std = r.gen_std;
+      g.amplitude = 0.0;
+      g.b_offset = sl.b0;
+      if (la_gen_fill(bufs[t], d.in_dtype, d.B, d.H, d.N, d.d, d.in_sb, d.in_sh, d.in_sn, &g, st) != 0)
+        return LA_ERR_HIP;
+    }
+    q = gq; k = gk; v = gv;
+    o = (char*)rq.o + (size_t)sl.b0 * member_tensor_bytes(d, d.out_dtype);
+    blk += 3 * tb;
+  } else {
+    const int64_t ie = esize(d.in_dtype), oe = esize(d.out_dtype);
+    q = (const char*)r.q + sl.b0 * d.in_sb * ie;
+    k = (const char*)r.k + sl.b0 * d.in_sb * ie;
+    v = (const char*)r.v + sl.b0 * d.in_sb * ie;
+    o = (char*)r.o + sl.b0 * d.out_sb * oe;
+  }
+  size_t ws = 0;
+  la_workspace_size(&d, 0, &ws);
+  double* S = rq.s + (size_t)sl.b0 * d.H * d.d * d.d;
+  double* z = rq.z + (size_t)sl.b0 * d.H * d.d;
+  la_status st2 = la_forward(&d, q, k, v, o, S, z, blk, ws, st);
+  if (st2 != LA_OK) return st2;
+  if (hipEventRecord(sl.done, st) != hipSuccess) return LA_ERR_HIP;
+  return LA_OK;
+}
+
+void finish_slice(la_server* s, Slice& sl, bool ok) {
+  s->arena.release(sl.off, sl.bytes);
+  if (sl.done) s->events.push_back(sl.done);
+  auto it = s->reqs.find(sl.req);
+  if (it == s->reqs.end()) return;
+  Request& rq = it->second;
+  rq.slices_done += 1;
+  if (!ok && !rq.failed) {
+    rq.failed = true;
+    rq.error = LA_ERR_HIP;
+  }
+  const bool all_admitted = rq.next_member >= rq.spec.desc.B;
+  if (all_admitted && rq.slices_done == rq.slices_started) {
+    rq.t_done = now_ns();
+    rq.state = rq.failed ? LA_REQ_FAILED : LA_REQ_DONE;
+    if (rq.failed) s->n_failed += 1; else s->n_completed += 1;
+  }
+}
+
+// Retire finished slices; returns how many finished.
+int retire(la_server* s) {
+  int n = 0;
+  const uint64_t t = now_ns();
+  for (size_t i = 0; i < s->inflight.size();) {
+    Slice& sl = s->inflight[i];
+    bool done = false, ok = true;
+    if (s->cfg.fake_executor) {
+      done = t >= sl.t_fake_done;
+    } else {
+      const hipError_t e = hipEventQuery(sl.done);
+      if (e == hipSuccess) done = true;
+      else if (e != hipErrorNotReady) { done = true; ok = false; }
+    }
+    if (done) {
+      finish_slice(s, sl, ok);
+      s->inflight[i] = s->inflight.back();
+      s->inflight.pop_back();
+      ++n;
+    } else {
+      ++i;
+    }
+  }
+  return n;
+}
+
+// Admit slices of the FIFO head while a slot and budget allow.
+int admit(la_server* s) {
+  int n = 0;
+  if (s->paused && !s->stopping) return 0;
+  while (!s->fifo.empty() && (int)s->inflight.size() < s->cfg.max_slots) {
+    const uint64_t id = s->fifo.front();
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) { s->fifo.pop_front(); continue; }
+    Request& rq = it->second;
+    const la_request& r = rq.spec;
+    if (!rq.keep_held) {
+      size_t off;
+      if (!s->arena.alloc(keep_bytes(r), &off)) break;
+      rq.keep_held = true;
+      rq.keep_off = off;
+      rq.keep_bytes = keep_bytes(r);
+      char* p = s->base ? s->base + off : nullptr;
+      const la_attn_desc& d = r.desc;
+      rq.s = (double*)p;
+      rq.z = (double*)(p ? p + align_up((size_t)(d.B * d.H * d.d * d.d) * 8) : nullptr);
+      if (r.generate)
+        rq.o = p ? p + align_up((size_t)(d.B * d.H * d.d * d.d) * 8) +
+                       align_up((size_t)(d.B * d.H * d.d) * 8)
+                 : nullptr;
+      else
+        rq.o = r.o;
+    }
+    // largest member count that fits the biggest free block
+    int64_t left = r.desc.B - rq.next_member;
+    int64_t m = left;
+    if (s->cfg.max_members_per_slice > 0) m = std::min<int64_t>(m, s->cfg.max_members_per_slice);
+    const size_t room = s->arena.largest_free();
+    while (m > 0 && slice_bytes(r, m) > room) m = m > 8 ? m * 3 / 4 : m - 1;
+    if (m <= 0) break;
+    Slice sl{};
+    sl.req = id;
+    sl.index = rq.slices_started;
+    sl.b0 = rq.next_member;
+    sl.m = m;
+    sl.bytes = slice_bytes(r, m);
+    if (!s->arena.alloc(sl.bytes, &sl.off)) break;
+    sl.stream = s->next_stream;
+    s->next_stream = (s->next_stream + 1) % std::max(1, (int)s->streams.size());
+    sl.done = take_event(s);
+    sl.fail = s->fail_at.count({id, sl.index}) > 0;
+    if (!s->cfg.fake_executor && !sl.done) { s->arena.release(sl.off, sl.bytes); break; }
+    if (rq.state == LA_REQ_QUEUED) {
+      rq.state = LA_REQ_RUNNING;
+      rq.t_admit = now_ns();
+    }
+    rq.next_member += m;
+    rq.slices_started += 1;
+    if (rq.next_member >= r.desc.B) s->fifo.pop_front();
+    const la_status st = launch_slice(s, rq, sl);
+    if (st != LA_OK) {
+      finish_slice(s, sl, false);
+    } else {
+      s->inflight.push_back(sl);
+    }
+    ++n;
+  }
+  return n;
+}
+
+void scheduler(la_server* s) {
+  if (!s->cfg.fake_executor) (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    const int changed = retire(s) + admit(s);
+    if (s->stopping && s->inflight.empty()) break;
+    if (changed) {
+      s->cv.notify_all();
+      continue;
+    }
+    // idle: wake on new work, or poll the device every 20 us
+    s->cv.wait_for(lk, std::chrono::microseconds(s->inflight.empty() ? 2000 : 20));
+  }
+  s->cv.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+la_status la_serve_create(const la_server_config* cfg, la_server** out) {
+  if (!cfg || !out) return LA_ERR_INVALID_ARG;
+  if (cfg->max_slots < 1 || cfg->n_streams < 1 || cfg->hbm_budget_bytes < kAlign ||
+      cfg->max_members_per_slice < 0 || cfg->fake_slice_ns < 0)
+    return LA_ERR_INVALID_ARG;
+  la_server* s = new la_server();
+  s->cfg = *cfg;
+  s->arena.init(cfg->hbm_budget_bytes);
+  if (!cfg->fake_executor) {
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->base, cfg->hbm_budget_bytes);
+    if (e != hipSuccess) {
+      delete s;
+      return e == hipErrorOutOfMemory ? LA_ERR_OOM : LA_ERR_HIP;
+    }
+    for (int i = 0; i < cfg->n_streams; ++i) {
+      hipStream_t st = nullptr;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        for (auto x : s->streams) (void)hipStreamDestroy(x);
+        (void)hipFree(s->base);
+        delete s;
+        return LA_ERR_HIP;
+      }
+      s->streams.push_back(st);
+    }
+  } else {
+    s->streams.resize(cfg->n_streams, nullptr);
+  }
+  s->th = std::thread(scheduler, s);
+  *out = s;
+  return LA_OK;
+}
+
+la_status la_serve_destroy(la_server* s) {
+  if (!s) return LA_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    // queued members are cancelled; admitted slices finish
+    for (uint64_t id : s->fifo) {
+      auto it = s->reqs.find(id);
+      if (it == s->reqs.end()) continue;
+      Request& rq = it->second;
+      rq.next_member = rq.spec.desc.B;
+      if (rq.slices_started == rq.slices_done) {
+        rq.state = LA_REQ_FAILED;
+        rq.error = LA_ERR_SHUTDOWN;
+        rq.t_done = now_ns();
+        s->n_failed += 1;
+      } else {
+        rq.failed = true;
+        rq.error = LA_ERR_SHUTDOWN;
+      }
+    }
+    s->fifo.clear();
+  }
+  s->cv.notify_all();
+  s->th.join();
+  if (!s->cfg.fake_executor) {
+    for (auto e : s->events) (void)hipEventDestroy(e);
+    for (auto st : s->streams) (void)hipStreamDestroy(st);
+    (void)hipFree(s->base);
+  }
+  delete s;
+  return LA_OK;
+}
+
+la_status la_serve_submit(la_server* s, const la_request* r, uint64_t* id) {
+  if (!s || !r || !id) return LA_ERR_INVALID_ARG;
+  la_request req = *r;
+  la_attn_desc& d = req.desc;
+  if (req.generate) {
+    if (r->q || r->k || r->v || r->o) return LA_ERR_INVALID_ARG;
+    if (!(req.gen_std > 0.0)) return LA_ERR_INVALID_ARG;
+    d.in_sn = d.d; d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh;
+    d.out_sn = d.d; d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh;
+  } else if (!s->cfg.fake_executor && (!r->q || !r->k || !r->v || !r->o)) {
+    return LA_ERR_INVALID_ARG;
+  }
+  size_t ws = 0;
+  la_status st = la_workspace_size(&d, 0, &ws);
+  if (st != LA_OK) return st;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) return LA_ERR_SHUTDOWN;
+  if (keep_bytes(req) + slice_bytes(req, 1) > s->arena.size()) {
+    s->n_rejected += 1;
+    return LA_ERR_OOM;
+  }
+  const uint64_t rid = s->next_id++;
+  Request rq;
+  rq.spec = req;
+  rq.t_arrival = req.t_arrival_ns ? req.t_arrival_ns : now_ns();
+  s->reqs.emplace(rid, rq);
+  s->fifo.push_back(rid);
+  s->n_submitted += 1;
+  *id = rid;
+  s->cv.notify_all();
+  return LA_OK;
+}
+
+la_status la_serve_poll(la_server* s, uint64_t id, la_result* out) {
+  if (!s || !out) return LA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
+  const Request& rq = it->second;
+  la_result r{};
+  r.state = rq.state;
+  r.error = rq.state == LA_REQ_FAILED ? rq.error : LA_OK;
+  r.t_arrival_ns = rq.t_arrival;
+  r.t_admit_ns = rq.t_admit;
+  r.t_done_ns = rq.t_done;
+  r.slices = rq.slices_started;
+  r.o = rq.o;
+  r.s = rq.s;
+  r.z = rq.z;
+  *out = r;
+  return LA_OK;
+}
+
+la_status la_serve_release(la_server* s, uint64_t id) {
+  if (!s) return LA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
+  Request& rq = it->second;
+  if (rq.state != LA_REQ_DONE && rq.state != LA_REQ_FAILED) return LA_ERR_BUSY;
+  if (rq.keep_held) s->arena.release(rq.keep_off, rq.keep_bytes);
+  s->reqs.erase(it);
+  s->cv.notify_all();
+  return LA_OK;
+}
+
+la_status la_serve_stats(la_server* s, la_serve_counters* out) {
+  if (!s || !out) return LA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  la_serve_counters r{};
+  r.submitted = s->n_submitted;
+  r.completed = s->n_completed;
+  r.failed = s->n_failed;
+  r.rejected = s->n_rejected;
+  r.queued = (int64_t)s->fifo.size();
+  r.in_flight_slices = (int64_t)s->inflight.size();
+  r.bytes_in_use = s->arena.in_use();
+  r.peak_bytes_in_use = s->arena.peak();
+  r.budget_bytes = s->arena.size();
+  *out = r;
+  return LA_OK;
+}
+
+la_status la_serve_debug_fail_slice(la_server* s, uint64_t id, int32_t slice) {
+  if (!s || slice < 0) return LA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
+  if (it->second.slices_started > slice) return LA_ERR_BUSY;  // already launched
+  s->fail_at.insert({id, slice});
+  return LA_OK;
+}
+
+la_status la_serve_debug_pause(la_server* s, int32_t paused) {
+  if (!s) return LA_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->paused = paused != 0;
+  }
+  s->cv.notify_all();
+  return LA_OK;
+}
+
+}  // extern "C"

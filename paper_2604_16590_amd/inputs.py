@@ -8,7 +8,8 @@ library ``liblagen.so``); both follow one definition:
   as easy as 1, 2, 3", SC 2011): a 10-round counter-based generator, round
   multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 /
   0xBB67AE85.
-* Element e of the logical [B, H, N, d] tensor (row-major flat index) takes
+* Element e of the logical [b_offset + B, H, N, d] tensor (row-major flat
+  index; a generated tensor holds batches b_offset .. b_offset + B - 1) takes
   pair index p = e >> 1, counter (lo32 p, hi32 p, stream, 0) and key
   (lo32 seed, hi32 seed).  From the first two output words
   u1 = ((x0 >> 9) + 0.5) * 2^-23 and u2 = (x1 >> 8) * 2^-24; Box-Muller in
@@ -70,6 +71,7 @@ class GenSpec:
     grid: tuple | None = None      # (T, n_lat, n_lon)
     amplitude: float = 1.0
     tensor_id: int = 0
+    b_offset: int = 0              # first logical batch index
 
 
 def normal_values(spec: GenSpec, flat_index: np.ndarray) -> np.ndarray:
@@ -125,7 +127,7 @@ def generate(spec: GenSpec, shape, dtype: str) -> np.ndarray:
     """A dense [B, H, N, d] tensor: uint16 bf16 bits or float32."""
     B, H, N, d = shape
     idx = np.arange(B * H * N * d, dtype=np.int64)
-    val = spec.mean + spec.std * normal_values(spec, idx)
+    val = spec.mean + spec.std * normal_values(spec, idx + spec.b_offset * H * N * d)
     val = val + structure_values(spec, B, H, N, d, idx)
     f = val.astype(np.float32).reshape(shape)
     if dtype == "bf16":

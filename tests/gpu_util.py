@@ -59,7 +59,15 @@ def max_rel(x, ref) -> float:
 
 
 def make_inputs(shape, dtype, seed, streams=(0, 1, 2), std=1.0, grid=None):
-    """Seeded host inputs (bf16 bits or float32), one per stream id."""
-    return [inputs.generate(inputs.GenSpec(seed=seed, stream=s, std=std, grid=grid,
-                                           tensor_id=s), shape, dtype)
-            for s in streams]
+    """Seeded inputs (host copies: bf16 bits or float32), one per stream id,
+    made by the device generator (liblagen.so, the same definition as the
+    host module paper_2604_16590_amd.inputs, which is much slower)."""
+    import paper_2604_16590_amd as la
+    dev = require_gpu()
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    out = []
+    for s in streams:
+        x = torch.empty(shape, dtype=tdt, device=dev)
+        la.gen_fill(x, seed=seed, stream_id=s, std=std, grid=grid, tensor_id=s)
+        out.append(to_host(x))
+    return out

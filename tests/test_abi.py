@@ -94,12 +94,12 @@ def test_forward_rejects_bad_pointers_before_gpu_work():
 
 def test_generator_rejects_bad_arguments():
     G = B.gen_lib()
-    spec = B.GenSpec(1, 0, 0, 0.0, 1.0, 0, 0, 0, 1.0)
+    spec = B.GenSpec(1, 0, 0, 0.0, 1.0, 0, 0, 0, 1.0, 0)
     fake = 1 << 20
     assert G.la_gen_fill(None, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
     assert G.la_gen_fill(fake + 2, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
     assert G.la_gen_fill(fake, 2, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(spec), None) == 1
-    grid = B.GenSpec(1, 0, 0, 0.0, 1.0, 2, 2, 3, 1.0)  # 12 tokens != N
+    grid = B.GenSpec(1, 0, 0, 0.0, 1.0, 2, 2, 3, 1.0, 0)  # 12 tokens != N
     assert G.la_gen_fill(fake, 0, 1, 1, 8, 16, 128, 128, 16, ctypes.byref(grid), None) == 1
 
 

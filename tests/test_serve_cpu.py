@@ -1,0 +1,173 @@
+"""Scheduler logic of the serving loop, on the CPU.
+
+The server runs with its fake executor: no GPU work, each admitted slice
+finishes a fixed time after launch.  Admission, slicing, the HBM budget,
+FIFO order, failure handling and shutdown are the same code as on the GPU.
+"""
+import threading
+import time
+
+import pytest
+
+from paper_2604_16590_amd import serve
+from paper_2604_16590_amd import _binding as B
+
+MS = 1_000_000
+
+
+def member_bytes(H, N, d, es=2):
+    return H * N * d * es
+
+
+def test_single_request_completes_with_ordered_stamps():
+    with serve.Server(1 << 30, fake_slice_ns=2 * MS) as srv:
+        rid = srv.submit(serve.desc_for(4, 2, 4096, 64), gen_seed=1)
+        r = srv.wait(rid)
+        assert r.state == serve.DONE and r.error == 0
+        assert r.t_arrival_ns <= r.t_admit_ns <= r.t_done_ns
+        assert r.t_done_ns - r.t_admit_ns >= 2 * MS
+        assert r.slices == 1
+        srv.release(rid)
+        with pytest.raises(B.LaError):
+            srv.poll(rid)
+
+
+def test_budget_splits_members_and_is_never_exceeded():
+    H, N, d = 2, 65536, 64
+    per_member = member_bytes(H, N, d)
+    # room for the kept output of 8 members plus about 3 members' inputs
+    budget = 8 * per_member + 3 * 3 * per_member + (8 << 20)
+    with serve.Server(budget, max_slots=4, fake_slice_ns=1 * MS) as srv:
+        rid = srv.submit(serve.desc_for(8, H, N, d), gen_seed=2)
+        r = srv.wait(rid)
+        assert r.state == serve.DONE
+        assert r.slices >= 3
+        c = srv.stats()
+        assert c.peak_bytes_in_use <= c.budget_bytes
+        srv.release(rid)
+        assert srv.stats().bytes_in_use == 0
+
+
+def test_max_members_per_slice():
+    with serve.Server(1 << 30, max_members_per_slice=3, fake_slice_ns=MS // 2) as srv:
+        rid = srv.submit(serve.desc_for(10, 1, 1024, 32), gen_seed=3)
+        assert srv.wait(rid).slices == 4
+
+
+def test_fifo_order_with_one_slot():
+    with serve.Server(1 << 30, max_slots=1, fake_slice_ns=3 * MS) as srv:
+        ids = [srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=i) for i in range(6)]
+        res = [srv.wait(i) for i in ids]
+        done = [r.t_done_ns for r in res]
+        admit = [r.t_admit_ns for r in res]
+        assert done == sorted(done) and admit == sorted(admit)
+        for a, b in zip(res, res[1:]):
+            assert b.t_admit_ns >= a.t_done_ns  # one slot: strictly one after another
+
+
+def test_slices_overlap_with_several_slots():
+    with serve.Server(1 << 30, max_slots=4, n_streams=4, fake_slice_ns=20 * MS) as srv:
+        t0 = time.monotonic_ns()
+        ids = [srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=i) for i in range(4)]
+        res = [srv.wait(i) for i in ids]
+        wall = max(r.t_done_ns for r in res) - t0
+        assert wall < 60 * MS  # four 20 ms slices ran concurrently, not back to back
+
+
+def test_request_too_large_for_budget_is_rejected():
+    with serve.Server(64 << 20, fake_slice_ns=MS) as srv:
+        with pytest.raises(B.LaError) as e:
+            srv.submit(serve.desc_for(1, 16, 1 << 20, 64), gen_seed=1)
+        assert e.value.status == 3  # LA_ERR_OOM
+        assert srv.stats().rejected == 1
+
+
+def test_injected_failure_fails_only_its_request():
+    with serve.Server(1 << 30, max_slots=1, max_members_per_slice=1, fake_slice_ns=10 * MS) as srv:
+        srv.pause()
+        blocker = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=0)
+        victim = srv.submit(serve.desc_for(3, 1, 1024, 64), gen_seed=1)
+        other = srv.submit(serve.desc_for(2, 1, 1024, 64), gen_seed=2)
+        srv.fail_slice(victim, 1)
+        srv.pause(False)
+        rb, rv, ro = srv.wait(blocker), srv.wait(victim), srv.wait(other)
+        assert rb.state == serve.DONE and ro.state == serve.DONE
+        assert rv.state == serve.FAILED and rv.error == 4  # LA_ERR_HIP
+        c = srv.stats()
+        assert c.failed == 1 and c.completed == 2
+
+
+def test_unknown_ids_and_busy_release():
+    with serve.Server(1 << 30, fake_slice_ns=50 * MS) as srv:
+        with pytest.raises(B.LaError) as e:
+            srv.poll(12345)
+        assert e.value.status == 5
+        rid = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1)
+        with pytest.raises(B.LaError) as e:
+            srv.release(rid)
+        assert e.value.status == 7  # LA_ERR_BUSY while running
+        srv.wait(rid)
+        srv.release(rid)
+
+
+def test_pause_holds_admission():
+    with serve.Server(1 << 30, fake_slice_ns=MS) as srv:
+        srv.pause()
+        rid = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1)
+        time.sleep(0.02)
+        assert srv.poll(rid).state == serve.QUEUED
+        srv.pause(False)
+        assert srv.wait(rid).state == serve.DONE
+
+
+def test_destroy_with_work_in_flight_and_queued():
+    srv = serve.Server(1 << 30, max_slots=1, fake_slice_ns=30 * MS)
+    for i in range(5):
+        srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=i)
+    t0 = time.monotonic()
+    srv.close()  # drains the slice in flight, cancels the rest
+    assert time.monotonic() - t0 < 1.0
+
+
+def test_concurrent_submitters():
+    with serve.Server(1 << 30, max_slots=8, n_streams=4, fake_slice_ns=MS) as srv:
+        ids, lock = [], threading.Lock()
+
+        def client(seed):
+            for j in range(20):
+                rid = srv.submit(serve.desc_for(2, 1, 2048, 32), gen_seed=seed * 100 + j)
+                with lock:
+                    ids.append(rid)
+
+        ts = [threading.Thread(target=client, args=(i,)) for i in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        assert len(set(ids)) == 80
+        for rid in ids:
+            assert srv.wait(rid).state == serve.DONE
+            srv.release(rid)
+        c = srv.stats()
+        assert c.completed == 80 and c.bytes_in_use == 0 and c.queued == 0
+
+
+def test_invalid_config_and_request():
+    with pytest.raises(B.LaError):
+        serve.Server(1 << 30, max_slots=0, fake_slice_ns=MS)
+    with serve.Server(1 << 30, fake_slice_ns=MS) as srv:
+        bad = serve.desc_for(1, 1, 1024, 48)
+        with pytest.raises(B.LaError) as e:
+            srv.submit(bad, gen_seed=1)
+        assert e.value.status == 2
+        with pytest.raises(B.LaError):
+            srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1, gen_std=0.0)
+
+
+def test_poisson_driver_reports_latency_percentiles():
+    with serve.Server(8 << 30, max_slots=4, fake_slice_ns=MS) as srv:
+        res = serve.run_poisson(srv, 30, 500.0, seed=1, H=2, d=32, members=2,
+                                n_min=1024, n_max=8192)
+    assert res["completed"] == 30 and res["failed"] == 0
+    assert res["p50_ms"] <= res["p99_ms"] <= res["max_ms"]
+    assert res["p50_ms"] >= 1.0  # at least the slice time
