@@ -30,78 +30,84 @@ struct RowCfg {
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
   static constexpr int RB = Q4 * ES;
   static constexpr int RWD = RB >= 4 ? RB / 4 : 1;
-  static constexpr int TT = 2;  // 16-token tiles per operand read
+  // 16-token tiles per step sharing each LDS operand read (bf16); the fp32
+  // path is matrix-core bound and keeps one tile to stay within registers
+  static constexpr int TT = DT == DT_BF16 ? 2 : 1;
+  // per-lane run held as: bf16 -> packed words (NS*4, zero padded past Q4),
+  // fp32 -> one float per feature
+  static constexpr int PW = DT == DT_BF16 ? NS * 4 : Q4;
 };
 
-// bf16 operand run: phi of the lane's features, packed, plus the rounded
-// values as floats and phi'.
+// phi over the lane's run: bf16 packs phi rounded to bf16 (the values the
+// matrix cores use); fp32 keeps fp32 phi.  phi' is recovered as
+// min(phi, 1): it is 1 where x > 0 (phi >= 1 there) and phi(x) elsewhere.
 template <int DT, int D>
-__device__ __forceinline__ void phi_run(const uint32_t* w, bf16x8* ops, float* pr, float* dp) {
+__device__ __forceinline__ void phi_words(const uint32_t* w, uint32_t* pw) {
   using C = RowCfg<DT, D>;
   constexpr int Q4 = C::Q4;
   if constexpr (DT == DT_BF16) {
 #pragma unroll
-    for (int s = 0; s < C::NS; ++s) {
-      u32x4 pk;
-#pragma unroll
-      for (int pp = 0; pp < 4; ++pp) {
-        const int c0 = 8 * s + 2 * pp;
-        if (c0 < Q4) {
-          const float x0 = word_elem<DT>(w, c0), x1 = word_elem<DT>(w, c0 + 1);
-          const float p0 = phi<DT>(x0), p1 = phi<DT>(x1);
-          pk[pp] = pack_bf16(p0, p1);
-          pr[c0] = bf16lo(pk[pp]);
-          pr[c0 + 1] = bf16hi(pk[pp]);
-          dp[c0] = x0 > 0.0f ? 1.0f : p0;
-          dp[c0 + 1] = x1 > 0.0f ? 1.0f : p1;
-        } else {
-          pk[pp] = 0;
-        }
-      }
-      ops[s] = as_bf16x8(pk);
+    for (int k = 0; k < C::PW; ++k) {
+      const int c0 = 2 * k;
+      pw[k] = c0 < Q4 ? pack_bf16(phi<DT>(word_elem<DT>(w, c0)), phi<DT>(word_elem<DT>(w, c0 + 1)))
+                      : 0u;
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < Q4; ++c) {
-      const float x = word_elem<DT>(w, c);
-      pr[c] = phi<DT>(x);
-      dp[c] = x > 0.0f ? 1.0f : pr[c];
-    }
+    for (int c = 0; c < Q4; ++c) pw[c] = __float_as_uint(phi<DT>(word_elem<DT>(w, c)));
   }
 }
 
-// Raw bf16 words of a lane's run as matrix-core operands (zero padded).
-template <int D>
-__device__ __forceinline__ void raw_ops(const uint32_t* w, bf16x8* ops) {
-  constexpr int Q4 = D / 4;
-#pragma unroll
-  for (int s = 0; s < ImageCfg<D>::NS; ++s) {
-    u32x4 pk;
-#pragma unroll
-    for (int pp = 0; pp < 4; ++pp) {
-      const int c0 = 8 * s + 2 * pp;
-      pk[pp] = c0 < Q4 ? w[c0 >> 1] : 0u;
-    }
-    ops[s] = as_bf16x8(pk);
-  }
-}
-
-// acc[i] += A_image[i] x B (the lane's run); bf16 images hold hi then lo
-// words per (tile, k-step); `use_lo` selects the two-part operand.
-template <int DT, int D, bool USE_LO>
-__device__ __forceinline__ void image_times_run(const u32x4* simg, int lane, const bf16x8* bops,
-                                                const float* bf, f32x4* acc) {
+// Raw bf16 words of a lane's run, zero padded to whole k-steps.
+template <int DT, int D>
+__device__ __forceinline__ void raw_words(const uint32_t* w, uint32_t* pw) {
   using C = RowCfg<DT, D>;
+#pragma unroll
+  for (int k = 0; k < C::PW; ++k) {
+    if constexpr (DT == DT_BF16) pw[k] = 2 * k < C::Q4 ? w[k] : 0u;
+    else pw[k] = w[k];
+  }
+}
+
+// Value of feature c of a run held as words.
+template <int DT>
+__device__ __forceinline__ float run_val(const uint32_t* pw, int c) {
+  if constexpr (DT == DT_BF16) return (c & 1) ? bf16hi(pw[c >> 1]) : bf16lo(pw[c >> 1]);
+  else return __uint_as_float(pw[c]);
+}
+
+// acc[t][i] += A_image[i] x B_t (the run of tile t) for the TT tiles of a
+// step: every LDS operand read feeds TT matrix-core ops.  bf16 images hold
+// hi then lo words per (tile, k-step); with USE_LO both parts are applied,
+// otherwise the staged image holds hi words only.
+template <int DT, int D, bool USE_LO>
+__device__ __forceinline__ void image_times_runs(
+    const u32x4* simg, int lane,
+    const uint32_t (&pw)[RowCfg<DT, D>::TT][RowCfg<DT, D>::PW],
+    f32x4 (&acc)[RowCfg<DT, D>::TT][D / 16]) {
+  using C = RowCfg<DT, D>;
+  constexpr int TT = C::TT;
   if constexpr (DT == DT_BF16) {
 #pragma unroll
     for (int i = 0; i < C::NT; ++i) {
 #pragma unroll
       for (int s = 0; s < C::NS; ++s) {
+        bf16x8 b[TT];
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+          b[t] = as_bf16x8(u32x4{pw[t][4 * s], pw[t][4 * s + 1], pw[t][4 * s + 2], pw[t][4 * s + 3]});
         if constexpr (USE_LO) {
-          acc[i] = mfma_bf16(as_bf16x8(simg[((i * C::NS + s) * 2 + 0) * 64 + lane]), bops[s], acc[i]);
-          acc[i] = mfma_bf16(as_bf16x8(simg[((i * C::NS + s) * 2 + 1) * 64 + lane]), bops[s], acc[i]);
+          const bf16x8 hi = as_bf16x8(simg[((i * C::NS + s) * 2 + 0) * 64 + lane]);
+          const bf16x8 lo = as_bf16x8(simg[((i * C::NS + s) * 2 + 1) * 64 + lane]);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) {
+            acc[t][i] = mfma_bf16(hi, b[t], acc[t][i]);
+            acc[t][i] = mfma_bf16(lo, b[t], acc[t][i]);
+          }
         } else {
-          acc[i] = mfma_bf16(as_bf16x8(simg[(i * C::NS + s) * 64 + lane]), bops[s], acc[i]);
+          const bf16x8 hi = as_bf16x8(simg[(i * C::NS + s) * 64 + lane]);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) acc[t][i] = mfma_bf16(hi, b[t], acc[t][i]);
         }
       }
       if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
@@ -114,7 +120,10 @@ __device__ __forceinline__ void image_times_run(const u32x4* simg, int lane, con
       for (int s4 = 0; s4 < Q4 / 4; ++s4) {
         const u32x4 a = simg[(i * (Q4 / 4) + s4) * 64 + lane];
 #pragma unroll
-        for (int t4 = 0; t4 < 4; ++t4) acc[i] = mfma_f32(__uint_as_float(a[t4]), bf[4 * s4 + t4], acc[i]);
+        for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+            acc[t][i] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]), acc[t][i]);
       }
       if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
     }
@@ -189,41 +198,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   char* obase = (char*)dq + (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
 
   for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
-    uint32_t qw[TT][C::RWD], gw[TT][C::RWD];
+    uint32_t pq[TT][C::PW], pg[TT][C::PW];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
       const int64_t t = t0 + 16 * tt + n;
+      uint32_t qw[C::RWD], gw[C::RWD];
       if (t < wg_end) {
-        load_words<C::RB>(qbase + t * sn * C::ES, qw[tt]);
-        load_words<C::RB>(gbase + t * sn * C::ES, gw[tt]);
+        load_words<C::RB>(qbase + t * sn * C::ES, qw);
+        load_words<C::RB>(gbase + t * sn * C::ES, gw);
       } else {
 #pragma unroll
-        for (int w = 0; w < C::RWD; ++w) { qw[tt][w] = 0; gw[tt][w] = 0; }
+        for (int w = 0; w < C::RWD; ++w) { qw[w] = 0; gw[w] = 0; }
       }
+      phi_words<DT, D>(qw, pq[tt]);
+      raw_words<DT, D>(gw, pg[tt]);
     }
+    f32x4 acc[TT][NT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+      for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    image_times_runs<DT, D, true>(simg, lane, pg, acc);  // X = S G
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      bf16x8 gops[C::NS], qops[C::NS];
-      float pr[Q4], dp[Q4], gf[Q4];
-      phi_run<DT, D>(qw[tt], qops, pr, dp);
-      if constexpr (DT == DT_BF16) {
-        raw_ops<D>(gw[tt], gops);
-      } else {
-#pragma unroll
-        for (int c = 0; c < Q4; ++c) gf[c] = __uint_as_float(gw[tt][c]);
-      }
-      f32x4 acc[NT];
-#pragma unroll
-      for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-      image_times_run<DT, D, true>(simg, lane, gops, gf, acc);  // X = S G
       double den = 0.0, gn = 0.0;
 #pragma unroll
       for (int i = 0; i < NT; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int c = 4 * i + r;
-          den = fma((double)pr[c], zr[c], den);
-          gn = fma((double)pr[c], (double)acc[i][r], gn);
+          const double p = (double)run_val<DT>(pq[tt], c);
+          den = fma(p, zr[c], den);
+          gn = fma(p, (double)acc[tt][i][r], gn);
         }
       den = sum_groups(den);
       gn = sum_groups(gn);
@@ -237,7 +243,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = 4 * i + r;
-            out[c] = (float)(fma(-go, zr[c], (double)acc[i][r]) * rden) * dp[c];
+            const float dphi_c = fminf(run_val<DT>(pq[tt], c), 1.0f);
+            out[c] = (float)(fma(-go, zr[c], (double)acc[tt][i][r]) * rden) * dphi_c;
           }
         store_run<OT, Q4>(obase + t * osn * OES, out);
         if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go * rden)};
@@ -289,49 +296,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
 
   for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
-    uint32_t kw[TT][C::RWD], vw[TT][C::RWD];
+    uint32_t pk[TT][C::PW], pv[TT][C::PW];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
       const int64_t t = t0 + 16 * tt + n;
+      uint32_t kw[C::RWD], vw[C::RWD];
       if (t < wg_end) {
-        load_words<C::RB>(kbase + t * sn * C::ES, kw[tt]);
-        if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw[tt]);
+        load_words<C::RB>(kbase + t * sn * C::ES, kw);
+        if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw);
       } else {
 #pragma unroll
-        for (int w = 0; w < C::RWD; ++w) { kw[tt][w] = 0; vw[tt][w] = 0; }
+        for (int w = 0; w < C::RWD; ++w) { kw[w] = 0; vw[w] = 0; }
       }
+      phi_words<DT, D>(kw, pk[tt]);
+      if (DO_K) raw_words<DT, D>(vw, pv[tt]);
     }
+    if constexpr (DO_V) {
+      f32x4 acc[TT][NT];
 #pragma unroll
-    for (int tt = 0; tt < TT; ++tt) {
-      bf16x8 kops[C::NS], vops[C::NS];
-      float pr[Q4], dp[Q4], vf[Q4];
-      phi_run<DT, D>(kw[tt], kops, pr, dp);
-      const int64_t t = t0 + 16 * tt + n;
-      if constexpr (DO_V) {
-        f32x4 acc[NT];
+      for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-        for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        image_times_run<DT, D, false>(timg, lane, kops, pr, acc);
+        for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      image_times_runs<DT, D, false>(timg, lane, pk, acc);
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        const int64_t t = t0 + 16 * tt + n;
         if (t < wg_end) {
           float out[Q4];
 #pragma unroll
           for (int i = 0; i < NT; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[4 * i + r] = acc[i][r];
+            for (int r = 0; r < 4; ++r) out[4 * i + r] = acc[tt][i][r];
           store_run<OT, Q4>((char*)dv + out_head + t * osn * OES, out);
         }
       }
-      if constexpr (DO_K) {
-        if constexpr (DT == DT_BF16) {
-          raw_ops<D>(vw[tt], vops);
-        } else {
+    }
+    if constexpr (DO_K) {
+      f32x4 acc[TT][NT];
 #pragma unroll
-          for (int c = 0; c < Q4; ++c) vf[c] = __uint_as_float(vw[tt][c]);
-        }
-        f32x4 acc[NT];
+      for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-        for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        image_times_run<DT, D, false>(nimg, lane, vops, vf, acc);
+        for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      image_times_runs<DT, D, false>(nimg, lane, pv, acc);
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        const int64_t t = t0 + 16 * tt + n;
         if (t < wg_end) {
           float out[Q4];
 #pragma unroll
@@ -339,7 +348,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int c = 4 * i + r;
-              out[c] = (float)((double)acc[i][r] + dzr[c]) * dp[c];
+              const float dphi_c = fminf(run_val<DT>(pk[tt], c), 1.0f);
+              out[c] = (float)((double)acc[tt][i][r] + dzr[c]) * dphi_c;
             }
           store_run<OT, Q4>((char*)dk + out_head + t * osn * OES, out);
         }
