@@ -86,7 +86,7 @@ struct Layout {
 
 // Forward: [part][S64][z64][img].
 // Backward: [img][part][stash][dS64][dz64][dimg]; the stash holds two floats
-// per query token (1/den, dden) between the query kernel and the dS
+// per query token (1/den, -(dO . O)) between the query kernel and the dS
 // reduction, the only part of any workspace that grows with N.
 Layout layout_for(const la_attn_desc* d, int pass) {
   const int64_t BH = d->B * d->H, D = d->d;

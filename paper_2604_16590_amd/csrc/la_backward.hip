@@ -162,7 +162,7 @@ __device__ __forceinline__ void stage_image(u32x4* dst, const u32x4* src, int wo
 }
 
 // ---------------------------------------------------------------------------
-// Query kernel: dQ, plus (1/den, dden) per token for the dS/dz reduction.
+// Query kernel: dQ, plus (1/den, -(G . O)) per token for the dS/dz reduction.
 // LDS holds the N image of S (A[row = q feature c][k = value feature e]).
 // ---------------------------------------------------------------------------
 template <int DT, int OT, int D>
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
             out[c] = (float)(fma(-go, zr[c], (double)acc[tt][i][r]) * rden) * dphi_c;
           }
         store_run<OT, Q4>(obase + t * osn * OES, out);
-        if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go * rden)};
+        if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go)};
       }
     }
   }

@@ -43,7 +43,7 @@ struct SummaryCfg {
 
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
 // they add exactly nothing to S or z and the step itself needs no masks.
-// In the backward mode the per-token pair (1/den, dden) is loaded too.
+// In the backward mode the per-token pair (1/den, -(dO . O)) is loaded too.
 template <int DT, int D, int MODE>
 __device__ __forceinline__ void summary_load(const char* kp, const char* vp,
                                              const float2* stash,
@@ -73,8 +73,10 @@ __device__ __forceinline__ void summary_load(const char* kp, const char* vp,
 
 // One step of the summary: phi on the keys, register transpose, MFMAs.
 // MODE_FWD: rows = phi(k), columns = v, z += phi(k).
-// MODE_BWD: rows = phi(q), columns = dO / den, z += dden * phi(q), which
-// accumulates dS and dz of the backward pass.
+// MODE_BWD: rows = phi(q) / den, columns = dO, z += -(dO . O) phi(q) / den,
+// which accumulates dS = sum phi(q) (dO / den)^T and dz = sum dden phi(q)
+// (dden = -(dO . O) / den) of the backward pass; the per-token pair
+// (1/den, -(dO . O)) comes from the query kernel.
 template <int DT, int D, int MODE>
 __device__ __forceinline__ void summary_step(
     const uint32_t (&kw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::KW],
@@ -92,14 +94,9 @@ __device__ __forceinline__ void summary_step(
       u32x4 w;
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
-        if constexpr (MODE == MODE_FWD) {
-          const uint32_t lo = word_bits16<DT>(vw[2 * pp], j);
-          const uint32_t hi = word_bits16<DT>(vw[2 * pp + 1], j);
-          w[pp] = lo | (hi << 16);
-        } else {
-          w[pp] = pack_bf16(word_elem<DT>(vw[2 * pp], j) * tok[2 * pp].x,
-                            word_elem<DT>(vw[2 * pp + 1], j) * tok[2 * pp + 1].x);
-        }
+        const uint32_t lo = word_bits16<DT>(vw[2 * pp], j);
+        const uint32_t hi = word_bits16<DT>(vw[2 * pp + 1], j);
+        w[pp] = lo | (hi << 16);
       }
       bv[j] = as_bf16x8(w);
     }
@@ -108,8 +105,12 @@ __device__ __forceinline__ void summary_step(
       uint32_t pk[4];
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
-        const float p0 = phi<DT>(word_elem<DT>(kw[2 * pp], i));
-        const float p1 = phi<DT>(word_elem<DT>(kw[2 * pp + 1], i));
+        float p0 = phi<DT>(word_elem<DT>(kw[2 * pp], i));
+        float p1 = phi<DT>(word_elem<DT>(kw[2 * pp + 1], i));
+        if constexpr (MODE == MODE_BWD) {
+          p0 *= tok[2 * pp].x;
+          p1 *= tok[2 * pp + 1].x;
+        }
         pk[pp] = pack_bf16(p0, p1);
         if constexpr (MODE == MODE_FWD) {
           // normaliser from the same rounded phi values that feed S
@@ -130,15 +131,16 @@ __device__ __forceinline__ void summary_step(
 #pragma unroll
       for (int i = 0; i < FR; ++i) {
         pk[i] = phi<DT>(word_elem<DT>(kw[r], i));
-        if constexpr (MODE == MODE_FWD) zacc[i] += pk[i];
-        else zacc[i] = fmaf(tok[r].y, pk[i], zacc[i]);
+        if constexpr (MODE == MODE_FWD) {
+          zacc[i] += pk[i];
+        } else {
+          pk[i] *= tok[r].x;
+          zacc[i] = fmaf(tok[r].y, pk[i], zacc[i]);
+        }
       }
       float vv[F];
 #pragma unroll
-      for (int j = 0; j < F; ++j) {
-        vv[j] = word_elem<DT>(vw[r], j);
-        if constexpr (MODE == MODE_BWD) vv[j] *= tok[r].x;
-      }
+      for (int j = 0; j < F; ++j) vv[j] = word_elem<DT>(vw[r], j);
 #pragma unroll
       for (int i = 0; i < FR; ++i)
 #pragma unroll

@@ -97,7 +97,7 @@ struct BwdArgs {
   int P, Tw, Ta;
   void* img;           // images of S
   float* part;         // partials of dS, dz
-  float2* stash;       // [BH][N] per query token: (1/den, dden)
+  float2* stash;       // [BH][N] per query token: (1/den, -(dO . O))
   double* dS64;
   double* dz64;
   void* dimg;          // images of dS
@@ -108,7 +108,7 @@ enum { MODE_FWD = 0, MODE_BWD = 1 };
 
 hipError_t launch_forward(const FwdArgs& a);
 // Token-reduction kernel: forward summary (MODE_FWD) or the dS/dz sums of
-// the backward (MODE_BWD, k = Q, v = dO, stash = per-token (1/den, dden)).
+// the backward (MODE_BWD, k = Q, v = dO, stash = per-token (1/den, -(dO . O))).
 hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v, int64_t sb,
                           int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
                           int Tw, const float2* stash, float* part, hipStream_t stream);
