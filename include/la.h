@@ -97,7 +97,7 @@ la_status la_version(int32_t* major, int32_t* minor);
 
 /*
  * Device workspace the caller must provide for a pass (0 = forward,
- * 1 = backward), in bytes, 256-byte aligned.  The forward's size depends on
+ * 1 = backward, 2 = apply), in bytes, 256-byte aligned.  The forward's size depends on
  * (B, H, d, dtype) and on N only through the number of per-tile partial
  * sums, which is capped, so it is bounded independently of N: the state of
  * linear attention per head is O(d^2), whatever the token count.  The
@@ -117,6 +117,19 @@ la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* byte
 la_status la_forward(const la_attn_desc* desc, const void* q, const void* k,
                      const void* v, void* o, double* s_out, double* z_out,
                      void* ws, size_t ws_bytes, la_stream stream);
+
+/*
+ * Apply a given summary: O_i = phi(q_i)^T S / (phi(q_i) . z) for every query,
+ * with S [B][H][d][d] and z [B][H][d] FP64 (dense) from an earlier
+ * la_forward (s_out, z_out).  This is the per-step work when the keys and
+ * values stay fixed while the queries change, as in the paper's temporal
+ * cross-attention against a compressed history (Sec. III-B) evaluated at
+ * every diffusion step (Sec. V, 80 steps per ensemble sample): the summary
+ * is computed once and only Q is streamed.  Same conventions as
+ * la_forward; ws_bytes >= la_workspace_size(desc, 2).
+ */
+la_status la_apply(const la_attn_desc* desc, const void* q, const double* s,
+                   const double* z, void* o, void* ws, size_t ws_bytes, la_stream stream);
 
 /*
  * Backward pass of L = <O, dO>: writes (does not accumulate) dq, dk, dv in

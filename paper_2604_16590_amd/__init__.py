@@ -3,9 +3,9 @@
 The attention runs in hand-written gfx950 HIP kernels behind the C ABI of
 liblinattn.so (include/la.h); this package is its Python binding.
 """
-from ._binding import (LaError, LinearAttention, Plan, backward, forward,  # noqa: F401
+from ._binding import (LaError, LinearAttention, Plan, apply, backward, forward,  # noqa: F401
                        gen_fill, lib, linear_attention, profile_enable, profile_read,
                        workspace_size)
 
-__all__ = ["forward", "backward", "LinearAttention", "linear_attention", "gen_fill",
+__all__ = ["forward", "apply", "backward", "LinearAttention", "linear_attention", "gen_fill",
            "workspace_size", "lib", "LaError", "Plan", "profile_enable", "profile_read"]

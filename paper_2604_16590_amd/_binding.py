@@ -69,7 +69,8 @@ def lib():
         L.la_workspace_size.argtypes = [DP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.la_forward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
         L.la_backward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
-        for name in ("la_version", "la_workspace_size", "la_forward", "la_backward"):
+        L.la_apply.argtypes = [DP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
+        for name in ("la_version", "la_workspace_size", "la_forward", "la_backward", "la_apply"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -162,6 +163,25 @@ def forward(q, k, v, out_dtype=None, return_summary=False, out=None):
         S.data_ptr() if S is not None else None, z.data_ptr() if z is not None else None,
         ws.data_ptr(), ws.numel(), _stream(q.device)))
     return (out, S, z) if return_summary else out
+
+
+def apply(q, S, z, out_dtype=None, out=None):
+    """O from queries and a summary (S, z) computed earlier by forward()."""
+    if not q.is_cuda:
+        raise ValueError("inputs must be GPU tensors")
+    B, H, N, d = q.shape
+    if S.shape != (B, H, d, d) or z.shape != (B, H, d) or S.dtype != torch.float64 \
+            or z.dtype != torch.float64:
+        raise ValueError("S must be [B,H,d,d] and z [B,H,d], float64")
+    S = S.contiguous()
+    z = z.contiguous()
+    if out is None:
+        out = torch.empty((B, H, N, d), dtype=out_dtype or q.dtype, device=q.device)
+    desc = make_desc(q, out)
+    ws = _workspace(workspace_size(desc, 2), q.device)
+    _check("la_apply", lib().la_apply(ctypes.byref(desc), q.data_ptr(), S.data_ptr(), z.data_ptr(),
+                                      out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return out
 
 
 def backward(q, k, v, S, z, dout, grad_dtype=None):

@@ -84,7 +84,7 @@ struct Layout {
   size_t part, S64, z64, img, stash, dS64, dz64, dimg, total;
 };
 
-// Forward: [part][S64][z64][img].
+// Forward: [part][S64][z64][img].  Apply: [img].
 // Backward: [img][part][stash][dS64][dz64][dimg]; the stash holds two floats
 // per query token (1/den, -(dO . O)) between the query kernel and the dS
 // reduction, the only part of any workspace that grows with N.
@@ -97,7 +97,9 @@ Layout layout_for(const la_attn_desc* d, int pass) {
   const size_t img = align_up((size_t)BH * head_image_bytes((int)D, d->in_dtype));
   Layout L{};
   size_t off = 0;
-  if (pass == 0) {
+  if (pass == 2) {
+    L.img = off; off += img;
+  } else if (pass == 0) {
     L.part = off; off += part;
     L.S64 = off; off += mat;
     L.z64 = off; off += vec;
@@ -142,7 +144,7 @@ la_status la_version(int32_t* major, int32_t* minor) {
 }
 
 la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* bytes) {
-  if (!bytes || (pass != 0 && pass != 1)) return LA_ERR_INVALID_ARG;
+  if (!bytes || pass < 0 || pass > 2) return LA_ERR_INVALID_ARG;
   la_status st = check_desc(desc);
   if (st != LA_OK) return st;
   *bytes = layout_for(desc, pass).total;
@@ -175,6 +177,33 @@ la_status la_forward(const la_attn_desc* desc, const void* q, const void* k,
   a.img = w + L.img;
   a.stream = (hipStream_t)stream;
   hipError_t e = la::launch_forward(a);
+  if (e != hipSuccess) return hip_fail(e);
+  return LA_OK;
+}
+
+la_status la_apply(const la_attn_desc* desc, const void* q, const double* s,
+                   const double* z, void* o, void* ws, size_t ws_bytes, la_stream stream) {
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  if (!q || !s || !z || !o || !ws) return LA_ERR_INVALID_ARG;
+  if (!aligned16(q) || !aligned16(o)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)s & 7u) || ((uintptr_t)z & 7u)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
+  const Layout L = layout_for(desc, 2);
+  if (ws_bytes < L.total) return LA_ERR_OOM;
+  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  la::FwdArgs a{};
+  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
+  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
+  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
+  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
+  a.q = q; a.o = o;
+  a.Ta = t.Ta;
+  a.S64 = const_cast<double*>(s);
+  a.z64 = const_cast<double*>(z);
+  a.img = (char*)ws + L.img;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = la::launch_apply(a);
   if (e != hipSuccess) return hip_fail(e);
   return LA_OK;
 }

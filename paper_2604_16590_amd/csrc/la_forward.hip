@@ -448,6 +448,9 @@ hipError_t launch_combine(const float* part, int P, double* M64, double* v64, vo
 }
 
 template <int D>
+static hipError_t launch_apply_only(const FwdArgs& a);
+
+template <int D>
 static hipError_t launch_forward_d(const FwdArgs& a) {
   const int BH = (int)(a.B * a.H);
   launch_summary_d<D>(MODE_FWD, a.in_dt, a.k, a.v, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
@@ -457,6 +460,12 @@ static hipError_t launch_forward_d(const FwdArgs& a) {
     ProfScope prof("combine", a.stream);
     combine_kernel<D><<<cgrid, 256, 0, a.stream>>>(a.part, a.P, a.S64, a.z64, a.img, a.in_dt);
   }
+  return launch_apply_only<D>(a);
+}
+
+template <int D>
+static hipError_t launch_apply_only(const FwdArgs& a) {
+  const int BH = (int)(a.B * a.H);
   dim3 agrid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
   ProfScope prof("apply", a.stream);
 #define LA_APPLY(DTI, DTO)                                                       \
@@ -476,6 +485,18 @@ hipError_t launch_forward(const FwdArgs& a) {
     case 32: return launch_forward_d<32>(a);
     case 64: return launch_forward_d<64>(a);
     case 128: return launch_forward_d<128>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply(const FwdArgs& a) {
+  hipError_t e = launch_images(a.S64, a.img, a.in_dt, a.B * a.H, a.D, a.stream);
+  if (e != hipSuccess) return e;
+  switch (a.D) {
+    case 16: return launch_apply_only<16>(a);
+    case 32: return launch_apply_only<32>(a);
+    case 64: return launch_apply_only<64>(a);
+    case 128: return launch_apply_only<128>(a);
   }
   return hipErrorInvalidValue;
 }

@@ -107,6 +107,8 @@ struct BwdArgs {
 enum { MODE_FWD = 0, MODE_BWD = 1 };
 
 hipError_t launch_forward(const FwdArgs& a);
+// Apply only: images of a given S (into a.img), then the apply kernel.
+hipError_t launch_apply(const FwdArgs& a);
 // Token-reduction kernel: forward summary (MODE_FWD) or the dS/dz sums of
 // the backward (MODE_BWD, k = Q, v = dO, stash = per-token (1/den, -(dO . O))).
 hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v, int64_t sb,

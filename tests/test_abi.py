@@ -61,6 +61,8 @@ def test_workspace_size_valid_and_bounded_in_N():
                              out_sb=2 * (1 << 30) * 64, out_sh=(1 << 30) * 64))
     assert st == 0 and big <= 2 * small  # capped number of partial sums
     assert ws_status(desc(), 1)[0] == 0
+    assert ws_status(desc(), 2)[0] == 0
+    assert ws_status(desc(), 3)[0] == 1
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -90,6 +92,10 @@ def test_forward_rejects_bad_pointers_before_gpu_work():
     assert L.la_backward(ctypes.byref(d), *args[:3], None, fake, fake, fake, fake, fake, fake,
                          ws.value, None) == 1
     assert L.la_forward(None, *args, None, None, fake, ws.value, None) == 1
+    L.la_workspace_size(ctypes.byref(d), 2, ctypes.byref(ws))
+    assert L.la_apply(ctypes.byref(d), fake, None, fake, fake, fake, ws.value, None) == 1
+    assert L.la_apply(ctypes.byref(d), fake, fake + 4, fake, fake, fake, ws.value, None) == 1
+    assert L.la_apply(ctypes.byref(d), fake, fake, fake, fake, fake, ws.value - 1, None) == 3
 
 
 def test_generator_rejects_bad_arguments():

@@ -206,3 +206,19 @@ def test_config3_long_context_sampled_heads():
     vmax = xs[2].float().amax(dim=2, keepdim=True)
     of = o.float()
     assert bool(((of >= vmin) & (of <= vmax)).all())
+
+
+def test_apply_reuses_summary_bitwise_and_for_new_queries():
+    # keys/values fixed, queries change (one diffusion step after another)
+    dev = require_gpu()
+    shape = (2, 3, 7000, 64)
+    q, k, v = make_inputs(shape, "bf16", 21)
+    (q2,) = make_inputs(shape, "bf16", 22, streams=(0,))
+    tq, tk, tv, tq2 = (to_device(x, dev) for x in (q, k, v, q2))
+    o, S, z = la.forward(tq, tk, tv, return_summary=True)
+    o_again = la.apply(tq, S, z)
+    o2 = la.apply(tq2, S, z)
+    torch.cuda.synchronize()
+    assert torch.equal(o, o_again)
+    _, S_ref, z_ref = oracle.forward(q, k, v, want_summary=True)
+    assert normwise(as64(o2), oracle.apply(q2, S_ref, z_ref)) < TOL["bf16"]
