@@ -11,9 +11,9 @@
  *    logical [b_offset + B, H, N, d] tensor (row-major flat index; the
  *    filled tensor is its batches b_offset .. b_offset + B - 1) uses counter
  *    (lo32(e>>1), hi32(e>>1), stream, 0) and key (lo32(seed), hi32(seed)).
- *  - u1 = ((x0 >> 9) + 0.5) * 2^-23, u2 = (x1 >> 8) * 2^-24; Box-Muller in
- *    FP64: r = sqrt(-2 ln u1), t = 2 pi u2; even e takes r cos t, odd e
- *    takes r sin t.
+ *  - u1 = ((x0 >> 9) + 0.5) * 2^-23, u2 = (x1 >> 8) * 2^-24 (exact in
+ *    FP32); Box-Muller in FP32: r = sqrt(-2 ln u1), t = 2 pi u2; even e takes
+ *    r cos t, odd e takes r sin t.
  *  - value = mean + std * normal (+ grid structure when grid_T > 0):
  *    token n = (t*n_lat + i)*n_lon + j; channel c of tensor `tensor_id`
  *    and head h adds amplitude * sin(m_c lon_j + l_c lat_i + 2 pi t/T + psi)
@@ -22,10 +22,11 @@
  *    psi = 2 pi frac(0.6180339887 (tensor_id*H*d + h*d + c)).
  *    The paper's temporal-scaling runs use 32 x 64 patch grids per frame
  *    (Sec. IV, Table of maximal sequence lengths).
- *  - The FP64 value is rounded to float32, then (for bfloat16) float32 ->
- *    bfloat16 round to nearest even.
- * Transcendentals may differ from the host's in the last FP64 bit, so the
- * two generators agree to within one rounding of the stored type.
+ *  - All of it in FP32 (mean + std * normal + grid term), then (for
+ *    bfloat16) float32 -> bfloat16 round to nearest even.
+ * Transcendentals may differ from the host's in the last bits, so the two
+ * generators agree to within a few FP32 ulps (one bf16 rounding).
+ * Limits: B*H <= 65535, N*d < 2^32.
  */
 #ifndef LA_GEN_H
 #define LA_GEN_H

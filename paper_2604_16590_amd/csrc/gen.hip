@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/la_gen.h"
 
 namespace {
@@ -38,55 +40,60 @@ struct GenArgs {
   uint64_t seed;
   uint32_t stream;
   int tensor_id;
-  double mean, std;
+  float mean, std;
   int grid_T, grid_lat, grid_lon;
-  double amplitude;
+  float amplitude;
   int64_t b_offset;
 };
 
-__device__ __forceinline__ double structure(const GenArgs& a, int64_t h, int64_t n, int64_t c) {
-  const double kPi = 3.14159265358979323846;
-  const int64_t nlon = a.grid_lon, nlat = a.grid_lat;
-  const int64_t j = n % nlon, i = (n / nlon) % nlat, t = n / (nlon * nlat);
-  const double lat = kPi * (((double)i + 0.5) / (double)nlat - 0.5);
-  const double lon = 2.0 * kPi * (double)j / (double)nlon;
-  const double m = (double)(1 + c % 4), l = (double)(1 + c % 3);
-  const double key = 0.6180339887 * (double)(a.tensor_id * a.H * a.d + h * a.d + c);
-  const double psi = 2.0 * kPi * (key - floor(key));
-  return a.amplitude * sin(m * lon + l * lat + 2.0 * kPi * (double)t / (double)a.grid_T + psi);
+// Grid term of channel c, head h, token n (FP32).
+__device__ __forceinline__ float structure(const GenArgs& a, int h, uint32_t n, uint32_t c) {
+  const float kPi = 3.14159265358979f;
+  const uint32_t nlon = (uint32_t)a.grid_lon, nlat = (uint32_t)a.grid_lat;
+  const uint32_t j = n % nlon, i = (n / nlon) % nlat, t = n / (nlon * nlat);
+  const float lat = kPi * (((float)i + 0.5f) / (float)nlat - 0.5f);
+  const float lon = 2.0f * kPi * (float)j / (float)nlon;
+  const float m = (float)(1 + c % 4), l = (float)(1 + c % 3);
+  const float key = 0.6180339887f * (float)(a.tensor_id * (int)a.H * (int)a.d + h * (int)a.d + (int)c);
+  const float psi = 2.0f * kPi * (key - floorf(key));
+  return a.amplitude * sinf(m * lon + l * lat + 2.0f * kPi * (float)t / (float)a.grid_T + psi);
 }
 
+// Grid: y = (b, h) of the filled tensor, x strides over the head's element
+// pairs (a pair shares one Philox call and one Box-Muller transform).
 __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
-  const int64_t pairs = a.B * a.H * a.N * a.d / 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const double kTwoPi = 6.28318530717958647692;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += stride) {
-    // logical pair index in the [b_offset + B, H, N, d] tensor
-    const int64_t lp = p + a.b_offset * a.H * a.N * a.d / 2;
-    uint32_t c[4] = {(uint32_t)lp, (uint32_t)((uint64_t)lp >> 32), a.stream, 0u};
+  const int64_t bh = blockIdx.y;
+  const int64_t b = bh / a.H, h = bh % a.H;
+  const uint32_t d = (uint32_t)a.d;
+  const int64_t head_pairs = a.N * a.d / 2;
+  const int64_t base = ((a.b_offset + b) * a.H + h) * head_pairs;  // logical pair index
+  char* head = (char*)a.dst + (b * a.sb + h * a.sh) * (a.dtype == 0 ? 2 : 4);
+  const float kTwoPi = 6.28318530717959f;
+  for (int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pl < head_pairs;
+       pl += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lp = (uint64_t)(base + pl);
+    uint32_t c[4] = {(uint32_t)lp, (uint32_t)(lp >> 32), a.stream, 0u};
     philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-    const double u1 = ((double)(c[0] >> 9) + 0.5) * 0x1p-23;
-    const double u2 = (double)(c[1] >> 8) * 0x1p-24;
-    const double r = sqrt(-2.0 * log(u1));
-    const double t = kTwoPi * u2;
-    const double z[2] = {r * cos(t), r * sin(t)};
-    const int64_t e0 = 2 * p;
-    const int64_t cc = e0 % a.d, n = (e0 / a.d) % a.N;
-    const int64_t h = (e0 / (a.d * a.N)) % a.H, b = e0 / (a.d * a.N * a.H);
-    const int64_t off = b * a.sb + h * a.sh + n * a.sn + cc;
+    const float u1 = ((float)(c[0] >> 9) + 0.5f) * 0x1p-23f;
+    const float u2 = (float)(c[1] >> 8) * 0x1p-24f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    const float t = kTwoPi * u2;
+    const float z[2] = {r * cosf(t), r * sinf(t)};
+    const uint32_t e0 = (uint32_t)(2 * pl);  // element within the head (N * d < 2^32)
+    const uint32_t n = e0 / d, cc = e0 - n * d;
     float f[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      double val = a.mean + a.std * z[s];
-      if (a.grid_T > 0) val += structure(a, h, n, cc + s);
-      f[s] = (float)val;
+      float val = a.mean + a.std * z[s];
+      if (a.grid_T > 0) val += structure(a, (int)h, n, cc + s);
+      f[s] = val;
     }
+    const int64_t off = (int64_t)n * a.sn + cc;
     if (a.dtype == 0) {
       const uint32_t w = (uint32_t)f32_to_bf16_rne(f[0]) | ((uint32_t)f32_to_bf16_rne(f[1]) << 16);
-      *(uint32_t*)((uint16_t*)a.dst + off) = w;
+      *(uint32_t*)((uint16_t*)head + off) = w;
     } else {
-      float2 w = {f[0], f[1]};
-      *(float2*)((float*)a.dst + off) = w;
+      *(float2*)((float*)head + off) = float2{f[0], f[1]};
     }
   }
 }
@@ -98,6 +105,7 @@ extern "C" int32_t la_gen_fill(void* dst, int32_t dtype, int64_t B, int64_t H, i
                                const la_gen_spec* spec, void* stream) {
   if (!dst || !spec || (dtype != 0 && dtype != 1)) return 1;
   if (B < 1 || H < 1 || N < 1 || d < 2 || (d & 1)) return 1;
+  if (B * H > 65535 || N * d >= (int64_t(1) << 32)) return 1;  // grid.y and 32-bit element index
   if (((uintptr_t)dst & 15u) != 0 || sb < 0 || sh < 0 || sn < d) return 1;
   if ((sb & 1) || (sh & 1) || (sn & 1)) return 1;  // pairs are stored as one word
   if (spec->grid_T < 0) return 1;
@@ -109,14 +117,16 @@ extern "C" int32_t la_gen_fill(void* dst, int32_t dtype, int64_t B, int64_t H, i
   a.dst = dst; a.dtype = dtype;
   a.B = B; a.H = H; a.N = N; a.d = d; a.sb = sb; a.sh = sh; a.sn = sn;
   a.seed = spec->seed; a.stream = spec->stream; a.tensor_id = spec->tensor_id;
-  a.mean = spec->mean; a.std = spec->std;
+  a.mean = (float)spec->mean; a.std = (float)spec->std;
   a.grid_T = spec->grid_T; a.grid_lat = spec->grid_lat; a.grid_lon = spec->grid_lon;
-  a.amplitude = spec->amplitude;
+  a.amplitude = (float)spec->amplitude;
   a.b_offset = spec->b_offset;
   if (a.b_offset < 0) return 1;
-  const int64_t pairs = B * H * N * d / 2;
-  int64_t blocks = (pairs + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(gen_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+  const int64_t head_pairs = N * d / 2;
+  int64_t bx = (head_pairs + 255) / 256;
+  const int64_t cap = std::max<int64_t>(1, 16384 / (B * H));  // ~16K blocks in total
+  if (bx > cap) bx = cap;
+  hipLaunchKernelGGL(gen_kernel, dim3((unsigned)bx, (unsigned)(B * H)), dim3(256), 0,
+                     (hipStream_t)stream, a);
   return hipGetLastError() == hipSuccess ? 0 : 4;
 }

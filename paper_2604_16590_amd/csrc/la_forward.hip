@@ -26,10 +26,11 @@ namespace la {
 // These FP32 per-wave sums are written out; combine_kernel adds them in
 // FP64 in partial order.
 // ---------------------------------------------------------------------------
-template <int DT, int D>
+template <int DT, int D, int MODE = MODE_FWD>
 struct SummaryCfg {
   static constexpr int F = D / 16;                 // features per lane (S tile grid is F x F)
-  static constexpr int SPLIT = D >= 128 ? 2 : 1;   // waves sharing one token range
+  // waves sharing one token range, each owning F/SPLIT rows of S tiles
+  static constexpr int SPLIT = D >= 128 ? (MODE == MODE_BWD ? 4 : 2) : 1;
   static constexpr int FR = F / SPLIT;             // S tile rows per wave
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
   static constexpr int KB = FR * ES;               // key bytes per lane per token
@@ -38,34 +39,42 @@ struct SummaryCfg {
   static constexpr int VW = VB >= 4 ? VB / 4 : 1;
   static constexpr int R = DT == DT_BF16 ? 8 : 4;  // tokens per lane group per step
   static constexpr int STEP = 4 * R;               // tokens per wave per step
-  static constexpr int PPB = 4 / SPLIT;            // partials per 4-wave block
+  // With SPLIT > 1 a workgroup is the SPLIT waves of one partial: each loads
+  // its share of the value features and the shares are swapped through LDS,
+  // so V is read from HBM once although every wave needs all of it.
+  static constexpr int THREADS = SPLIT > 1 ? 64 * SPLIT : 256;
+  static constexpr int PPB = SPLIT > 1 ? 1 : 4;    // partials per workgroup
+  static constexpr int VWH = VW / SPLIT;           // value words a wave loads per row
 };
 
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
 // they add exactly nothing to S or z and the step itself needs no masks.
 // In the backward mode the per-token pair (1/den, -(dO . O)) is loaded too.
+// `vw` receives this wave's value words: all of them (SPLIT = 1) or its
+// share (words [VWH*part, VWH*part + VWH)).
 template <int DT, int D, int MODE>
 __device__ __forceinline__ void summary_load(const char* kp, const char* vp,
                                              const float2* stash,
                                              int64_t row_bytes, int64_t t0, int g,
                                              int64_t t_end, bool partial,
-                                             uint32_t (&kw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::KW],
-                                             uint32_t (&vw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::VW],
-                                             float2 (&tok)[SummaryCfg<DT, D>::R]) {
-  using C = SummaryCfg<DT, D>;
+                                             uint32_t (&kw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::KW],
+                                             uint32_t (&vw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::VW],
+                                             float2 (&tok)[SummaryCfg<DT, D, MODE>::R], int half) {
+  using C = SummaryCfg<DT, D, MODE>;
   const uint32_t neg_inf = DT == DT_BF16 ? 0xff80ff80u : 0xff800000u;
 #pragma unroll
   for (int r = 0; r < C::R; ++r) {
     const int64_t t = t0 + C::R * g + r;
+    uint32_t* vh = vw[r] + C::VWH * half;
     if (!partial || t < t_end) {
       load_words<C::KB>(kp + t * row_bytes, kw[r]);
-      load_words<C::VB>(vp + t * row_bytes, vw[r]);
+      load_words<C::VB / C::SPLIT>(vp + t * row_bytes, vh);
       if constexpr (MODE == MODE_BWD) tok[r] = stash[t];
     } else {
 #pragma unroll
       for (int w = 0; w < C::KW; ++w) kw[r][w] = neg_inf;
 #pragma unroll
-      for (int w = 0; w < C::VW; ++w) vw[r][w] = 0;
+      for (int w = 0; w < C::VWH; ++w) vh[w] = 0;
       if constexpr (MODE == MODE_BWD) tok[r] = float2{0.f, 0.f};
     }
   }
@@ -79,12 +88,12 @@ __device__ __forceinline__ void summary_load(const char* kp, const char* vp,
 // (1/den, -(dO . O)) comes from the query kernel.
 template <int DT, int D, int MODE>
 __device__ __forceinline__ void summary_step(
-    const uint32_t (&kw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::KW],
-    const uint32_t (&vw)[SummaryCfg<DT, D>::R][SummaryCfg<DT, D>::VW],
-    const float2 (&tok)[SummaryCfg<DT, D>::R],
-    f32x4 (&acc)[SummaryCfg<DT, D>::FR][SummaryCfg<DT, D>::F],
-    float (&zacc)[SummaryCfg<DT, D>::FR]) {
-  using C = SummaryCfg<DT, D>;
+    const uint32_t (&kw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::KW],
+    const uint32_t (&vw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::VW],
+    const float2 (&tok)[SummaryCfg<DT, D, MODE>::R],
+    f32x4 (&acc)[SummaryCfg<DT, D, MODE>::FR][SummaryCfg<DT, D, MODE>::F],
+    float (&zacc)[SummaryCfg<DT, D, MODE>::FR]) {
+  using C = SummaryCfg<DT, D, MODE>;
   constexpr int F = C::F, FR = C::FR;
   if constexpr (DT == DT_BF16) {
     // Value operands: token pairs of one feature packed into words.
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     const void* __restrict__ k, const void* __restrict__ v, int64_t sb,
     int64_t sh, int64_t sn, int H, int64_t N, int P, int Tw,
     const float2* __restrict__ stash, float* __restrict__ part) {
-  using C = SummaryCfg<DT, D>;
+  using C = SummaryCfg<DT, D, MODE>;
   constexpr int F = C::F, FR = C::FR;
   constexpr int E = D * D + D;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -170,9 +179,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const int64_t t_begin = (int64_t)p * Tw;
   const int64_t t_end = min(N, t_begin + (int64_t)Tw);
   const int64_t head = (b * sb + h * sh) * C::ES;
-  // lane m reads key features [F*m + FR*half, +FR) and value features [F*m, +F)
+  // lane m reads key features [F*m + FR*half, +FR) and value features
+  // [F*m + (F/SPLIT)*half, +F/SPLIT) (all F of them when SPLIT = 1)
   const char* kp = (const char*)k + head + (int64_t)(F * m + FR * half) * C::ES;
-  const char* vp = (const char*)v + head + (int64_t)m * C::VB;
+  const char* vp = (const char*)v + head + (int64_t)m * C::VB + (int64_t)half * (C::VB / C::SPLIT);
   const int64_t row_bytes = sn * C::ES;
 
   f32x4 acc[FR][F];
@@ -185,10 +195,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   for (int i = 0; i < FR; ++i) zacc[i] = 0.f;
 
   const float2* tstash = MODE == MODE_BWD ? stash + (int64_t)bh * N : nullptr;
+  // value shares swapped between the SPLIT waves, double buffered:
+  // [buffer][share][row][word][lane]
+  __shared__ uint32_t vex[C::SPLIT > 1 ? 2 * C::SPLIT * C::R * C::VWH * 64 : 1];
+  int buf = 0;
   for (int64_t t0 = t_begin; t0 < t_end; t0 += C::STEP) {
     uint32_t kw[C::R][C::KW], vw[C::R][C::VW];
     float2 tok[C::R];
-    summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0, g, t_end, t0 + C::STEP > t_end, kw, vw, tok);
+    summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0, g, t_end, t0 + C::STEP > t_end, kw, vw,
+                              tok, half);
+    if constexpr (C::SPLIT > 1) {
+      uint32_t* mine = vex + ((buf * C::SPLIT + half) * C::R) * C::VWH * 64;
+#pragma unroll
+      for (int r = 0; r < C::R; ++r)
+#pragma unroll
+        for (int w = 0; w < C::VWH; ++w) mine[(r * C::VWH + w) * 64 + lane] = vw[r][C::VWH * half + w];
+      __syncthreads();
+#pragma unroll
+      for (int o = 1; o < C::SPLIT; ++o) {
+        const int other = (half + o) % C::SPLIT;
+        const uint32_t* src = vex + ((buf * C::SPLIT + other) * C::R) * C::VWH * 64;
+#pragma unroll
+        for (int r = 0; r < C::R; ++r)
+#pragma unroll
+          for (int w = 0; w < C::VWH; ++w) vw[r][C::VWH * other + w] = src[(r * C::VWH + w) * 64 + lane];
+      }
+      buf ^= 1;
+    }
     summary_step<DT, D, MODE>(kw, vw, tok, acc, zacc);
   }
 

@@ -13,11 +13,10 @@ library ``liblagen.so``); both follow one definition:
   pair index p = e >> 1, counter (lo32 p, hi32 p, stream, 0) and key
   (lo32 seed, hi32 seed).  From the first two output words
   u1 = ((x0 >> 9) + 0.5) * 2^-23 and u2 = (x1 >> 8) * 2^-24; Box-Muller in
-  FP64 gives r = sqrt(-2 ln u1), t = 2 pi u2, and the element takes
+  FP32 gives r = sqrt(-2 ln u1), t = 2 pi u2, and the element takes
   r cos t (even e) or r sin t (odd e).
-* value = mean + std * normal (+ the optional grid structure below), in FP64,
-  rounded to float32, then (for bfloat16) float32 -> bfloat16 round to
-  nearest even.
+* value = mean + std * normal (+ the optional grid structure below), all in
+  FP32, then (for bfloat16) float32 -> bfloat16 round to nearest even.
 * Grid structure (spatiotemporal token grids of T frames x lat x lon
   patches): token n = (t * n_lat + i) * n_lon + j, lat_i = pi((i+1/2)/n_lat
   - 1/2), lon_j = 2 pi j / n_lon.  Channel c of tensor x (0 = Q, 1 = K,
@@ -81,12 +80,13 @@ def normal_values(spec: GenSpec, flat_index: np.ndarray) -> np.ndarray:
     x0, x1, _, _ = philox4x32_10(p & np.uint64(MASK), p >> np.uint64(32),
                                  np.full_like(p, spec.stream), np.zeros_like(p),
                                  spec.seed & MASK, (spec.seed >> 32) & MASK)
-    u1 = ((x0 >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
-    u2 = (x1 >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
-    r = np.sqrt(-2.0 * np.log(u1))
-    t = 2.0 * math.pi * u2
+    f32 = np.float32
+    u1 = ((x0 >> np.uint64(9)).astype(f32) + f32(0.5)) * f32(2.0 ** -23)
+    u2 = (x1 >> np.uint64(8)).astype(f32) * f32(2.0 ** -24)
+    r = np.sqrt(f32(-2.0) * np.log(u1))
+    t = f32(6.28318530717959) * u2
     odd = (e & np.uint64(1)).astype(bool)
-    return np.where(odd, r * np.sin(t), r * np.cos(t))
+    return np.where(odd, r * np.sin(t), r * np.cos(t)).astype(f32)
 
 
 def structure_values(spec: GenSpec, B, H, N, d, flat_index) -> np.ndarray:
@@ -100,13 +100,16 @@ def structure_values(spec: GenSpec, B, H, N, d, flat_index) -> np.ndarray:
     j = n % nlon
     i = (n // nlon) % nlat
     t = n // (nlon * nlat)
-    lat = math.pi * ((i + 0.5) / nlat - 0.5)
-    lon = 2.0 * math.pi * j / nlon
-    m = 1 + c % 4
-    l = 1 + c % 3
-    key = spec.tensor_id * H * d + h * d + c
-    psi = 2.0 * math.pi * np.modf(0.6180339887 * key)[0]
-    return spec.amplitude * np.sin(m * lon + l * lat + 2.0 * math.pi * t / T + psi)
+    f32 = np.float32
+    pi = f32(3.14159265358979)
+    lat = pi * ((i.astype(f32) + f32(0.5)) / f32(nlat) - f32(0.5))
+    lon = f32(2.0) * pi * j.astype(f32) / f32(nlon)
+    m = (1 + c % 4).astype(f32)
+    l = (1 + c % 3).astype(f32)
+    key = f32(0.6180339887) * (spec.tensor_id * H * d + h * d + c).astype(f32)
+    psi = f32(2.0) * pi * (key - np.floor(key))
+    arg = m * lon + l * lat + f32(2.0) * pi * t.astype(f32) / f32(T) + psi
+    return (f32(spec.amplitude) * np.sin(arg)).astype(f32)
 
 
 def f32_to_bf16_bits(x: np.ndarray) -> np.ndarray:
@@ -127,8 +130,10 @@ def generate(spec: GenSpec, shape, dtype: str) -> np.ndarray:
     """A dense [B, H, N, d] tensor: uint16 bf16 bits or float32."""
     B, H, N, d = shape
     idx = np.arange(B * H * N * d, dtype=np.int64)
-    val = spec.mean + spec.std * normal_values(spec, idx + spec.b_offset * H * N * d)
-    val = val + structure_values(spec, B, H, N, d, idx)
+    f32 = np.float32
+    val = f32(spec.mean) + f32(spec.std) * normal_values(spec, idx + spec.b_offset * H * N * d)
+    if spec.grid is not None:
+        val = val + structure_values(spec, B, H, N, d, idx)
     f = val.astype(np.float32).reshape(shape)
     if dtype == "bf16":
         return f32_to_bf16_bits(f)
