@@ -36,6 +36,9 @@ struct RowCfg {
   // per-lane run held as: bf16 -> packed words (NS*4, zero padded past Q4),
   // fp32 -> one float per feature
   static constexpr int PW = DT == DT_BF16 ? NS * 4 : Q4;
+  // prefetch one step ahead, except where it would not fit the registers
+  // of two waves per SIMD (d = 128, and fp32 from d = 64)
+  static constexpr bool PF = D < 128 && !(DT == DT_FP32 && D >= 64);
 };
 
 // phi over the lane's run: bf16 packs phi rounded to bf16 (the values the
@@ -197,21 +200,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const char* gbase = (const char*)dout + in_head;
   char* obase = (char*)dq + (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
 
-  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
+  auto load_one = [&](int64_t t0, uint32_t* qw, uint32_t* gw) {
+    const int64_t t = t0 + n;
+    if (t < wg_end) {
+      load_words<C::RB>(qbase + t * sn * C::ES, qw);
+      load_words<C::RB>(gbase + t * sn * C::ES, gw);
+    } else {
+#pragma unroll
+      for (int w = 0; w < C::RWD; ++w) { qw[w] = 0; gw[w] = 0; }
+    }
+  };
+  auto load = [&](int64_t t0, uint32_t (&qw)[C::PF ? TT : 1][C::RWD],
+                  uint32_t (&gw)[C::PF ? TT : 1][C::RWD]) {
+#pragma unroll
+    for (int tt = 0; tt < (C::PF ? TT : 1); ++tt) load_one(t0 + 16 * tt, qw[tt], gw[tt]);
+  };
+  uint32_t qcur[C::PF ? TT : 1][C::RWD], gcur[C::PF ? TT : 1][C::RWD];
+  const int64_t first = wg_begin + 16 * TT * wave;
+  if constexpr (C::PF) {
+    if (first < wg_end) load(first, qcur, gcur);
+  }
+  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
+    // next step's inputs are in flight while this step computes
+    uint32_t qnext[C::PF ? TT : 1][C::RWD], gnext[C::PF ? TT : 1][C::RWD];
+    const bool more = C::PF && t0 + 16 * TT * 4 < wg_end;
     uint32_t pq[TT][C::PW], pg[TT][C::PW];
+    if constexpr (C::PF) {
+      if (more) load(t0 + 16 * TT * 4, qnext, gnext);
 #pragma unroll
-    for (int tt = 0; tt < TT; ++tt) {
-      const int64_t t = t0 + 16 * tt + n;
-      uint32_t qw[C::RWD], gw[C::RWD];
-      if (t < wg_end) {
-        load_words<C::RB>(qbase + t * sn * C::ES, qw);
-        load_words<C::RB>(gbase + t * sn * C::ES, gw);
-      } else {
-#pragma unroll
-        for (int w = 0; w < C::RWD; ++w) { qw[w] = 0; gw[w] = 0; }
+      for (int tt = 0; tt < TT; ++tt) {
+        phi_words<DT, D>(qcur[tt], pq[tt]);
+        raw_words<DT, D>(gcur[tt], pg[tt]);
       }
-      phi_words<DT, D>(qw, pq[tt]);
-      raw_words<DT, D>(gw, pg[tt]);
+    } else {
+      // load and convert one tile at a time (fewer live registers)
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        uint32_t one_q[1][C::RWD], one_g[1][C::RWD];
+        load_one(t0 + 16 * tt, one_q[0], one_g[0]);
+        phi_words<DT, D>(one_q[0], pq[tt]);
+        raw_words<DT, D>(one_g[0], pg[tt]);
+      }
     }
     f32x4 acc[TT][NT];
 #pragma unroll
@@ -249,6 +278,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
         store_run<OT, Q4>(obase + t * osn * OES, out);
         if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go)};
       }
+    }
+    if (more) {
+#pragma unroll
+      for (int tt = 0; tt < (C::PF ? TT : 1); ++tt)
+#pragma unroll
+        for (int w = 0; w < C::RWD; ++w) { qcur[tt][w] = qnext[tt][w]; gcur[tt][w] = gnext[tt][w]; }
     }
   }
 }
@@ -295,21 +330,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const char* vbase = (const char*)v + in_head;
   const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
 
-  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
+  auto load_one = [&](int64_t t0, uint32_t* kw, uint32_t* vw) {
+    const int64_t t = t0 + n;
+    if (t < wg_end) {
+      load_words<C::RB>(kbase + t * sn * C::ES, kw);
+      if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw);
+    } else {
+#pragma unroll
+      for (int w = 0; w < C::RWD; ++w) { kw[w] = 0; vw[w] = 0; }
+    }
+  };
+  auto load = [&](int64_t t0, uint32_t (&kw)[C::PF ? TT : 1][C::RWD],
+                  uint32_t (&vw)[C::PF ? TT : 1][C::RWD]) {
+#pragma unroll
+    for (int tt = 0; tt < (C::PF ? TT : 1); ++tt) load_one(t0 + 16 * tt, kw[tt], vw[tt]);
+  };
+  uint32_t kcur[C::PF ? TT : 1][C::RWD], vcur[C::PF ? TT : 1][C::RWD];
+  const int64_t first = wg_begin + 16 * TT * wave;
+  if constexpr (C::PF) {
+    if (first < wg_end) load(first, kcur, vcur);
+  }
+  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
+    // next step's inputs are in flight while this step computes
+    uint32_t knext[C::PF ? TT : 1][C::RWD], vnext[C::PF ? TT : 1][C::RWD];
+    const bool more = C::PF && t0 + 16 * TT * 4 < wg_end;
     uint32_t pk[TT][C::PW], pv[TT][C::PW];
+    if constexpr (C::PF) {
+      if (more) load(t0 + 16 * TT * 4, knext, vnext);
 #pragma unroll
-    for (int tt = 0; tt < TT; ++tt) {
-      const int64_t t = t0 + 16 * tt + n;
-      uint32_t kw[C::RWD], vw[C::RWD];
-      if (t < wg_end) {
-        load_words<C::RB>(kbase + t * sn * C::ES, kw);
-        if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw);
-      } else {
-#pragma unroll
-        for (int w = 0; w < C::RWD; ++w) { kw[w] = 0; vw[w] = 0; }
+      for (int tt = 0; tt < TT; ++tt) {
+        phi_words<DT, D>(kcur[tt], pk[tt]);
+        if (DO_K) raw_words<DT, D>(vcur[tt], pv[tt]);
       }
-      phi_words<DT, D>(kw, pk[tt]);
-      if (DO_K) raw_words<DT, D>(vw, pv[tt]);
+    } else {
+      // load and convert one tile at a time (fewer live registers)
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        uint32_t one_k[C::RWD], one_v[C::RWD];
+        load_one(t0 + 16 * tt, one_k, one_v);
+        phi_words<DT, D>(one_k, pk[tt]);
+        if (DO_K) raw_words<DT, D>(one_v, pv[tt]);
+      }
     }
     if constexpr (DO_V) {
       f32x4 acc[TT][NT];
@@ -354,6 +415,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
           store_run<OT, Q4>((char*)dk + out_head + t * osn * OES, out);
         }
       }
+    }
+    if (more) {
+#pragma unroll
+      for (int tt = 0; tt < (C::PF ? TT : 1); ++tt)
+#pragma unroll
+        for (int w = 0; w < C::RWD; ++w) { kcur[tt][w] = knext[tt][w]; vcur[tt][w] = vnext[tt][w]; }
     }
   }
 }

@@ -29,53 +29,57 @@ namespace la {
 template <int DT, int D, int MODE = MODE_FWD>
 struct SummaryCfg {
   static constexpr int F = D / 16;                 // features per lane (S tile grid is F x F)
-  // waves sharing one token range, each owning F/SPLIT rows of S tiles
+  // waves sharing one token range; each owns F/SPLIT rows of S tiles and
+  // loads F/SPLIT of the value features, whose matrix-core operands it
+  // shares with the others through LDS, so K and V are each read once
   static constexpr int SPLIT = D >= 128 ? (MODE == MODE_BWD ? 4 : 2) : 1;
-  static constexpr int FR = F / SPLIT;             // S tile rows per wave
+  static constexpr int FR = F / SPLIT;             // S tile rows (key features) per wave
+  static constexpr int FC = F / SPLIT;             // value features loaded per wave
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
   static constexpr int KB = FR * ES;               // key bytes per lane per token
-  static constexpr int VB = F * ES;                // value bytes per lane per token
+  static constexpr int VB = FC * ES;               // value bytes per lane per token
   static constexpr int KW = KB >= 4 ? KB / 4 : 1;
   static constexpr int VW = VB >= 4 ? VB / 4 : 1;
   static constexpr int R = DT == DT_BF16 ? 8 : 4;  // tokens per lane group per step
   static constexpr int STEP = 4 * R;               // tokens per wave per step
-  // With SPLIT > 1 a workgroup is the SPLIT waves of one partial: each loads
-  // its share of the value features and the shares are swapped through LDS,
-  // so V is read from HBM once although every wave needs all of it.
   static constexpr int THREADS = SPLIT > 1 ? 64 * SPLIT : 256;
   static constexpr int PPB = SPLIT > 1 ? 1 : 4;    // partials per workgroup
-  static constexpr int VWH = VW / SPLIT;           // value words a wave loads per row
+  // LDS words exchanged per buffer: bf16 -> F operands x 4 words x 64 lanes;
+  // fp32 -> R tokens x F values x 64 lanes
+  static constexpr int XW = SPLIT > 1 ? (DT == DT_BF16 ? F * 4 * 64 : R * F * 64) : 1;
+};
+
+template <int DT, int D, int MODE>
+struct SummaryRegs {
+  using C = SummaryCfg<DT, D, MODE>;
+  uint32_t kw[C::R][C::KW];
+  uint32_t vw[C::R][C::VW];
+  float2 tok[C::R];
 };
 
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
 // they add exactly nothing to S or z and the step itself needs no masks.
 // In the backward mode the per-token pair (1/den, -(dO . O)) is loaded too.
-// `vw` receives this wave's value words: all of them (SPLIT = 1) or its
-// share (words [VWH*part, VWH*part + VWH)).
 template <int DT, int D, int MODE>
-__device__ __forceinline__ void summary_load(const char* kp, const char* vp,
-                                             const float2* stash,
-                                             int64_t row_bytes, int64_t t0, int g,
-                                             int64_t t_end, bool partial,
-                                             uint32_t (&kw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::KW],
-                                             uint32_t (&vw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::VW],
-                                             float2 (&tok)[SummaryCfg<DT, D, MODE>::R], int half) {
+__device__ __forceinline__ void summary_load(const char* kp, const char* vp, const float2* stash,
+                                             int64_t row_bytes, int64_t t0, int g, int64_t t_end,
+                                             SummaryRegs<DT, D, MODE>& x) {
   using C = SummaryCfg<DT, D, MODE>;
   const uint32_t neg_inf = DT == DT_BF16 ? 0xff80ff80u : 0xff800000u;
+  const bool partial = t0 + C::STEP > t_end;
 #pragma unroll
   for (int r = 0; r < C::R; ++r) {
     const int64_t t = t0 + C::R * g + r;
-    uint32_t* vh = vw[r] + C::VWH * half;
     if (!partial || t < t_end) {
-      load_words<C::KB>(kp + t * row_bytes, kw[r]);
-      load_words<C::VB / C::SPLIT>(vp + t * row_bytes, vh);
-      if constexpr (MODE == MODE_BWD) tok[r] = stash[t];
+      load_words<C::KB>(kp + t * row_bytes, x.kw[r]);
+      load_words<C::VB>(vp + t * row_bytes, x.vw[r]);
+      if constexpr (MODE == MODE_BWD) x.tok[r] = stash[t];
     } else {
 #pragma unroll
-      for (int w = 0; w < C::KW; ++w) kw[r][w] = neg_inf;
+      for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
 #pragma unroll
-      for (int w = 0; w < C::VWH; ++w) vh[w] = 0;
-      if constexpr (MODE == MODE_BWD) tok[r] = float2{0.f, 0.f};
+      for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
+      if constexpr (MODE == MODE_BWD) x.tok[r] = float2{0.f, 0.f};
     }
   }
 }
@@ -86,81 +90,104 @@ __device__ __forceinline__ void summary_load(const char* kp, const char* vp,
 // which accumulates dS = sum phi(q) (dO / den)^T and dz = sum dden phi(q)
 // (dden = -(dO . O) / den) of the backward pass; the per-token pair
 // (1/den, -(dO . O)) comes from the query kernel.
+// `xch` is this step's LDS exchange buffer (SPLIT > 1).
 template <int DT, int D, int MODE>
-__device__ __forceinline__ void summary_step(
-    const uint32_t (&kw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::KW],
-    const uint32_t (&vw)[SummaryCfg<DT, D, MODE>::R][SummaryCfg<DT, D, MODE>::VW],
-    const float2 (&tok)[SummaryCfg<DT, D, MODE>::R],
-    f32x4 (&acc)[SummaryCfg<DT, D, MODE>::FR][SummaryCfg<DT, D, MODE>::F],
-    float (&zacc)[SummaryCfg<DT, D, MODE>::FR]) {
+__device__ __forceinline__ void summary_step(const SummaryRegs<DT, D, MODE>& x, int part, int lane,
+                                             uint32_t* xch,
+                                             f32x4 (&acc)[SummaryCfg<DT, D, MODE>::FR][SummaryCfg<DT, D, MODE>::F],
+                                             float (&zacc)[SummaryCfg<DT, D, MODE>::FR]) {
   using C = SummaryCfg<DT, D, MODE>;
-  constexpr int F = C::F, FR = C::FR;
+  constexpr int F = C::F, FR = C::FR, FC = C::FC;
   if constexpr (DT == DT_BF16) {
-    // Value operands: token pairs of one feature packed into words.
-    bf16x8 bv[F];
+    // value operands of this wave's features: token pairs of one feature
+    // packed into words
+    uint32_t own[FC][4];
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-      u32x4 w;
+    for (int jj = 0; jj < FC; ++jj)
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
-        const uint32_t lo = word_bits16<DT>(vw[2 * pp], j);
-        const uint32_t hi = word_bits16<DT>(vw[2 * pp + 1], j);
-        w[pp] = lo | (hi << 16);
+        const uint32_t lo = word_bits16<DT>(x.vw[2 * pp], jj);
+        const uint32_t hi = word_bits16<DT>(x.vw[2 * pp + 1], jj);
+        own[jj][pp] = lo | (hi << 16);
       }
-      bv[j] = as_bf16x8(w);
+    if constexpr (C::SPLIT > 1) {
+#pragma unroll
+      for (int jj = 0; jj < FC; ++jj)
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) xch[((part * FC + jj) * 4 + pp) * 64 + lane] = own[jj][pp];
+      __syncthreads();
     }
+    // key operands of this wave's rows
+    bf16x8 ak[FR];
 #pragma unroll
     for (int i = 0; i < FR; ++i) {
       uint32_t pk[4];
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
-        float p0 = phi<DT>(word_elem<DT>(kw[2 * pp], i));
-        float p1 = phi<DT>(word_elem<DT>(kw[2 * pp + 1], i));
+        float p0 = phi<DT>(word_elem<DT>(x.kw[2 * pp], i));
+        float p1 = phi<DT>(word_elem<DT>(x.kw[2 * pp + 1], i));
         if constexpr (MODE == MODE_BWD) {
-          p0 *= tok[2 * pp].x;
-          p1 *= tok[2 * pp + 1].x;
+          p0 *= x.tok[2 * pp].x;
+          p1 *= x.tok[2 * pp + 1].x;
         }
         pk[pp] = pack_bf16(p0, p1);
         if constexpr (MODE == MODE_FWD) {
           // normaliser from the same rounded phi values that feed S
           zacc[i] = add_bf16_pair(zacc[i], pk[pp]);
         } else {
-          zacc[i] = fmaf(tok[2 * pp].y, bf16lo(pk[pp]), zacc[i]);
-          zacc[i] = fmaf(tok[2 * pp + 1].y, bf16hi(pk[pp]), zacc[i]);
+          zacc[i] = fmaf(x.tok[2 * pp].y, bf16lo(pk[pp]), zacc[i]);
+          zacc[i] = fmaf(x.tok[2 * pp + 1].y, bf16hi(pk[pp]), zacc[i]);
         }
       }
-      const bf16x8 ak = as_bf16x8(u32x4{pk[0], pk[1], pk[2], pk[3]});
+      ak[i] = as_bf16x8(u32x4{pk[0], pk[1], pk[2], pk[3]});
+    }
 #pragma unroll
-      for (int j = 0; j < F; ++j) acc[i][j] = mfma_bf16(ak, bv[j], acc[i][j]);
+    for (int j = 0; j < F; ++j) {
+      bf16x8 bv;
+      if constexpr (C::SPLIT > 1) {
+        bv = as_bf16x8(u32x4{xch[(j * 4 + 0) * 64 + lane], xch[(j * 4 + 1) * 64 + lane],
+                             xch[(j * 4 + 2) * 64 + lane], xch[(j * 4 + 3) * 64 + lane]});
+      } else {
+        bv = as_bf16x8(u32x4{own[j][0], own[j][1], own[j][2], own[j][3]});
+      }
+#pragma unroll
+      for (int i = 0; i < FR; ++i) acc[i][j] = mfma_bf16(ak[i], bv, acc[i][j]);
     }
   } else {
+    if constexpr (C::SPLIT > 1) {
+#pragma unroll
+      for (int r = 0; r < C::R; ++r)
+#pragma unroll
+        for (int jj = 0; jj < FC; ++jj) xch[(r * F + part * FC + jj) * 64 + lane] = x.vw[r][jj];
+      __syncthreads();
+    }
 #pragma unroll
     for (int r = 0; r < C::R; ++r) {
       float pk[FR];
 #pragma unroll
       for (int i = 0; i < FR; ++i) {
-        pk[i] = phi<DT>(word_elem<DT>(kw[r], i));
+        pk[i] = phi<DT>(word_elem<DT>(x.kw[r], i));
         if constexpr (MODE == MODE_FWD) {
           zacc[i] += pk[i];
         } else {
-          pk[i] *= tok[r].x;
-          zacc[i] = fmaf(tok[r].y, pk[i], zacc[i]);
+          pk[i] *= x.tok[r].x;
+          zacc[i] = fmaf(x.tok[r].y, pk[i], zacc[i]);
         }
       }
-      float vv[F];
 #pragma unroll
-      for (int j = 0; j < F; ++j) vv[j] = word_elem<DT>(vw[r], j);
+      for (int j = 0; j < F; ++j) {
+        const float vj = C::SPLIT > 1 ? __uint_as_float(xch[(r * F + j) * 64 + lane])
+                                      : word_elem<DT>(x.vw[r], j);
 #pragma unroll
-      for (int i = 0; i < FR; ++i)
-#pragma unroll
-        for (int j = 0; j < F; ++j)
-          acc[i][j] = mfma_f32(pk[i], vv[j], acc[i][j]);
+        for (int i = 0; i < FR; ++i) acc[i][j] = mfma_f32(pk[i], vj, acc[i][j]);
+      }
     }
   }
 }
 
-// Grid: x = blocks of PPB partials, y = (b, h).  Wave w of a block takes
-// partial p = x*PPB + w/SPLIT and S tile rows [FR*(w%SPLIT), +FR).
+// Grid: x = blocks of PPB partials, y = (b, h).  With SPLIT = 1 each wave of
+// a block takes its own partial; otherwise the block's SPLIT waves share
+// partial x, wave w owning S tile rows [FR*w, +FR).
 template <int DT, int D, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void summary_kernel(
     const void* __restrict__ k, const void* __restrict__ v, int64_t sb,
@@ -171,19 +198,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   constexpr int E = D * D + D;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, m = lane & 15;
-  const int p = blockIdx.x * C::PPB + wave / C::SPLIT;
-  const int half = wave % C::SPLIT;
-  if (p >= P) return;
+  const int p = C::SPLIT > 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + wave;
+  const int half = C::SPLIT > 1 ? wave : 0;
+  if (p >= P) return;  // uniform across a SPLIT group (it shares p)
   const int bh = blockIdx.y;
   const int64_t b = bh / H, h = bh % H;
   const int64_t t_begin = (int64_t)p * Tw;
   const int64_t t_end = min(N, t_begin + (int64_t)Tw);
   const int64_t head = (b * sb + h * sh) * C::ES;
   // lane m reads key features [F*m + FR*half, +FR) and value features
-  // [F*m + (F/SPLIT)*half, +F/SPLIT) (all F of them when SPLIT = 1)
+  // [F*m + FC*half, +FC)
   const char* kp = (const char*)k + head + (int64_t)(F * m + FR * half) * C::ES;
-  const char* vp = (const char*)v + head + (int64_t)m * C::VB + (int64_t)half * (C::VB / C::SPLIT);
+  const char* vp = (const char*)v + head + (int64_t)(F * m + C::FC * half) * C::ES;
   const int64_t row_bytes = sn * C::ES;
+  const float2* tstash = MODE == MODE_BWD ? stash + (int64_t)bh * N : nullptr;
 
   f32x4 acc[FR][F];
 #pragma unroll
@@ -194,35 +222,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 #pragma unroll
   for (int i = 0; i < FR; ++i) zacc[i] = 0.f;
 
-  const float2* tstash = MODE == MODE_BWD ? stash + (int64_t)bh * N : nullptr;
-  // value shares swapped between the SPLIT waves, double buffered:
-  // [buffer][share][row][word][lane]
-  __shared__ uint32_t vex[C::SPLIT > 1 ? 2 * C::SPLIT * C::R * C::VWH * 64 : 1];
+  // double-buffered exchange: one barrier per step suffices, because a
+  // buffer is rewritten only after the barrier of the step in between
+  __shared__ uint32_t xch[2 * C::XW];
   int buf = 0;
+  SummaryRegs<DT, D, MODE> cur;
+  summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t_begin, g, t_end, cur);
   for (int64_t t0 = t_begin; t0 < t_end; t0 += C::STEP) {
-    uint32_t kw[C::R][C::KW], vw[C::R][C::VW];
-    float2 tok[C::R];
-    summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0, g, t_end, t0 + C::STEP > t_end, kw, vw,
-                              tok, half);
-    if constexpr (C::SPLIT > 1) {
-      uint32_t* mine = vex + ((buf * C::SPLIT + half) * C::R) * C::VWH * 64;
-#pragma unroll
-      for (int r = 0; r < C::R; ++r)
-#pragma unroll
-        for (int w = 0; w < C::VWH; ++w) mine[(r * C::VWH + w) * 64 + lane] = vw[r][C::VWH * half + w];
-      __syncthreads();
-#pragma unroll
-      for (int o = 1; o < C::SPLIT; ++o) {
-        const int other = (half + o) % C::SPLIT;
-        const uint32_t* src = vex + ((buf * C::SPLIT + other) * C::R) * C::VWH * 64;
-#pragma unroll
-        for (int r = 0; r < C::R; ++r)
-#pragma unroll
-          for (int w = 0; w < C::VWH; ++w) vw[r][C::VWH * other + w] = src[(r * C::VWH + w) * 64 + lane];
-      }
-      buf ^= 1;
-    }
-    summary_step<DT, D, MODE>(kw, vw, tok, acc, zacc);
+    SummaryRegs<DT, D, MODE> nxt;
+    const bool more = t0 + C::STEP < t_end;
+    if (more) summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0 + C::STEP, g, t_end, nxt);
+    summary_step<DT, D, MODE>(cur, half, lane, xch + buf * C::XW, acc, zacc);
+    buf ^= 1;
+    if (more) cur = nxt;
   }
 
   // this wave's share of the partial: S tiles in lane order, then z
@@ -304,7 +316,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   constexpr int OB = Q4 * OES;
   constexpr int OW = OB >= 4 ? OB / 4 : 1;
   constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
-  constexpr int TT = 2;                       // 16-token tiles per operand read
+  // 16-token tiles per LDS operand read (fp32 at d = 128: one, for registers)
+  constexpr int TT = DT == DT_FP32 && D >= 128 ? 1 : 2;
   __shared__ u32x4 simg[IMG_WORDS];
 
   const int bh = blockIdx.y;
@@ -326,8 +339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const char* qbase = (const char*)q + (b * sb + h * sh) * ES + (int64_t)g * QB;
   char* obase = (char*)o + (b * osb + h * osh) * OES + (int64_t)g * OB;
 
-  for (int64_t t0 = wg_begin + 16 * TT * wave; t0 < wg_end; t0 += 16 * TT * 4) {
-    uint32_t qw[TT][QW];
+  auto load_q = [&](int64_t t0, uint32_t (&qw)[TT][QW]) {
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
       const int64_t t = t0 + 16 * tt + n;
@@ -338,6 +350,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
       }
     }
+  };
+  // prefetch one step ahead where the registers allow it
+  constexpr bool PF = true;
+  uint32_t qcur[TT][QW];
+  const int64_t first = wg_begin + 16 * TT * wave;
+  if (first < wg_end) load_q(first, qcur);
+  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
+    if constexpr (!PF) {
+      if (t0 != first) load_q(t0, qcur);  // no prefetch: this step's load
+    }
+    // next step's queries are in flight while this step computes
+    uint32_t qw[TT][QW], qnext[TT][QW];
+    const bool more = PF && t0 + 16 * TT * 4 < wg_end;
+    if (more) load_q(t0 + 16 * TT * 4, qnext);
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+      for (int w = 0; w < QW; ++w) qw[tt][w] = qcur[tt][w];
     // phi(q), the FP64 normaliser, and the matrix-core operands
     double den[TT];
     f32x4 acc[TT][NT];
@@ -429,6 +459,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
           }
         store_words<OB>(obase + t * osn * OES, ow);
       }
+    }
+    if (more) {
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+        for (int w = 0; w < QW; ++w) qcur[tt][w] = qnext[tt][w];
     }
   }
 }
