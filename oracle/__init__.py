@@ -78,6 +78,11 @@ def _load(path=None):
         lib.oracle_backward_query.argtypes = [i64, i64, i64, i64, T, T, dp, dp, dp, dp, dp]
         lib.oracle_backward_key.argtypes = [i64, i64, i64, i64, T, T, dp, dp, dp, dp]
         lib.oracle_threads.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_tile_extract.argtypes = [i64p, i64p, i64p, i64, dp, dp]
+        lib.oracle_tile_blend.argtypes = [i64p, i64p, i64p, i64, dp, dp]
+        lib.oracle_hann.restype = ctypes.c_double
+        lib.oracle_hann.argtypes = [i64, i64]
         _lib = lib
     return _lib
 
@@ -199,3 +204,40 @@ def backward_key(k, v, dS, dz):
     if rc:
         raise ValueError("oracle_backward_key rejected its arguments")
     return dk, dv
+
+
+def _tri(v):
+    return (ctypes.c_int64 * 3)(*[int(x) for x in v])
+
+
+def tile_geometry(dims, core, halo):
+    n = [-(-int(d) // int(c)) for d, c in zip(dims, core)]
+    L = [int(c) + 2 * int(h) for c, h in zip(core, halo)]
+    return n, L
+
+
+def tile_extract(x, core, halo):
+    """Tiles [n_tiles, Lt, Ly, Lx, C] (FP64) of a field x [T, Y, X, C]."""
+    x = np.ascontiguousarray(x, np.float64)
+    T, Y, X, C = x.shape
+    n, L = tile_geometry((T, Y, X), core, halo)
+    tiles = np.empty((n[0] * n[1] * n[2], L[0], L[1], L[2], C), np.float64)
+    rc = _load().oracle_tile_extract(_tri((T, Y, X)), _tri(core), _tri(halo), C, _dptr(x), _dptr(tiles))
+    if rc:
+        raise ValueError("oracle_tile_extract rejected its arguments")
+    return tiles
+
+
+def tile_blend(tiles, dims, core, halo):
+    """Hann-weighted overlap average of tiles back onto a [T, Y, X, C] field."""
+    tiles = np.ascontiguousarray(tiles, np.float64)
+    C = tiles.shape[-1]
+    out = np.empty(tuple(dims) + (C,), np.float64)
+    rc = _load().oracle_tile_blend(_tri(dims), _tri(core), _tri(halo), C, _dptr(tiles), _dptr(out))
+    if rc:
+        raise ValueError("oracle_tile_blend rejected its arguments")
+    return out
+
+
+def hann(u, L):
+    return _load().oracle_hann(int(u), int(L))

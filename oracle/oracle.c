@@ -284,3 +284,92 @@ int oracle_backward(int64_t B, int64_t H, int64_t N, int64_t d,
   if (!dz) free(dzb);
   return rc;
 }
+
+/* ---- tiles with halos and Hann-weighted overlap averaging ------------- */
+
+double oracle_hann(int64_t u, int64_t L) {
+  const double pi = 3.14159265358979323846;
+  const double sn = sin(pi * ((double)u + 0.5) / (double)L);
+  return sn * sn;
+}
+
+static int tile_args_bad(const int64_t* dims, const int64_t* core, const int64_t* halo,
+                         int64_t C) {
+  if (C < 1) return 1;
+  for (int k = 0; k < 3; ++k)
+    if (dims[k] < 1 || core[k] < 1 || halo[k] < 0 || halo[k] > core[k]) return 1;
+  return 0;
+}
+
+static int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+int oracle_tile_extract(const int64_t* dims, const int64_t* core, const int64_t* halo,
+                        int64_t C, const double* x, double* tiles) {
+  if (tile_args_bad(dims, core, halo, C) || !x || !tiles) return -1;
+  int64_t n[3], L[3];
+  for (int k = 0; k < 3; ++k) {
+    n[k] = ceil_div64(dims[k], core[k]);
+    L[k] = core[k] + 2 * halo[k];
+  }
+  const int64_t tile_elems = L[0] * L[1] * L[2] * C;
+#pragma omp parallel for schedule(static)
+  for (int64_t tile = 0; tile < n[0] * n[1] * n[2]; ++tile) {
+    const int64_t a = tile / (n[1] * n[2]), i = (tile / n[2]) % n[1], j = tile % n[2];
+    double* dst = tiles + tile * tile_elems;
+    for (int64_t ut = 0; ut < L[0]; ++ut)
+      for (int64_t uy = 0; uy < L[1]; ++uy)
+        for (int64_t ux = 0; ux < L[2]; ++ux) {
+          const int64_t gt = clamp64(a * core[0] - halo[0] + ut, 0, dims[0] - 1);
+          const int64_t gy = clamp64(i * core[1] - halo[1] + uy, 0, dims[1] - 1);
+          const int64_t gx = clamp64(j * core[2] - halo[2] + ux, 0, dims[2] - 1);
+          const double* src = x + ((gt * dims[1] + gy) * dims[2] + gx) * C;
+          double* d = dst + ((ut * L[1] + uy) * L[2] + ux) * C;
+          for (int64_t c = 0; c < C; ++c) d[c] = src[c];
+        }
+  }
+  return 0;
+}
+
+int oracle_tile_blend(const int64_t* dims, const int64_t* core, const int64_t* halo,
+                      int64_t C, const double* tiles, double* out) {
+  if (tile_args_bad(dims, core, halo, C) || !tiles || !out) return -1;
+  int64_t n[3], L[3];
+  for (int k = 0; k < 3; ++k) {
+    n[k] = ceil_div64(dims[k], core[k]);
+    L[k] = core[k] + 2 * halo[k];
+  }
+  const int64_t tile_elems = L[0] * L[1] * L[2] * C;
+  const int64_t npos = dims[0] * dims[1] * dims[2];
+  double* wsum = (double*)calloc((size_t)npos, sizeof(double));
+  for (int64_t p = 0; p < npos * C; ++p) out[p] = 0.0;
+  /* every tile adds w * D into the positions it covers, tiles in order */
+  for (int64_t tile = 0; tile < n[0] * n[1] * n[2]; ++tile) {
+    const int64_t a = tile / (n[1] * n[2]), i = (tile / n[2]) % n[1], j = tile % n[2];
+    const double* src = tiles + tile * tile_elems;
+    for (int64_t ut = 0; ut < L[0]; ++ut) {
+      const int64_t gt = a * core[0] - halo[0] + ut;
+      if (gt < 0 || gt >= dims[0]) continue;
+      for (int64_t uy = 0; uy < L[1]; ++uy) {
+        const int64_t gy = i * core[1] - halo[1] + uy;
+        if (gy < 0 || gy >= dims[1]) continue;
+        for (int64_t ux = 0; ux < L[2]; ++ux) {
+          const int64_t gx = j * core[2] - halo[2] + ux;
+          if (gx < 0 || gx >= dims[2]) continue;
+          const double w = oracle_hann(ut, L[0]) * oracle_hann(uy, L[1]) * oracle_hann(ux, L[2]);
+          const int64_t p = (gt * dims[1] + gy) * dims[2] + gx;
+          const double* d = src + ((ut * L[1] + uy) * L[2] + ux) * C;
+          for (int64_t c = 0; c < C; ++c) out[p * C + c] += w * d[c];
+          wsum[p] += w;
+        }
+      }
+    }
+  }
+  for (int64_t p = 0; p < npos; ++p)
+    for (int64_t c = 0; c < C; ++c) out[p * C + c] /= wsum[p];
+  free(wsum);
+  return 0;
+}

@@ -84,6 +84,27 @@ int oracle_backward_key(int64_t B, int64_t H, int64_t N, int64_t d,
                         oracle_tensor k, oracle_tensor v, const double* dS,
                         const double* dz, double* dk, double* dv);
 
+/*
+ * Tiles with halos and window-weighted overlap averaging (the paper's
+ * global propagation step, Sec. III-C).  A global field X [T][Y][X][C]
+ * (channels contiguous, FP64) is covered by tiles whose cores (ct, cy, cx)
+ * lie on a regular grid and which extend by halos (ht, hy, hx) <= the core
+ * on every side.  Tile (a, i, j) in row-major order covers positions
+ * [a ct - ht, (a+1) ct + ht) x [i cy - hy, ...) x [j cx - hx, ...); its
+ * array is [Lt][Ly][Lx][C] with L = core + 2 halo.
+ *  extract: tile value at a local position = X at the global position,
+ *           with coordinates clamped into the domain.
+ *  blend:   out(p) = sum_tiles w(p) D(p) / sum_tiles w(p) over the tiles
+ *           covering p, w = product over dims of sin^2(pi (u + 1/2) / L)
+ *           (Hann window at cell centres, u the local coordinate).
+ * Dimensions: dims[0..2] = (T, Y, X), core[0..2], halo[0..2], C.
+ */
+int oracle_tile_extract(const int64_t* dims, const int64_t* core, const int64_t* halo,
+                        int64_t C, const double* x, double* tiles);
+int oracle_tile_blend(const int64_t* dims, const int64_t* core, const int64_t* halo,
+                      int64_t C, const double* tiles, double* out);
+double oracle_hann(int64_t u, int64_t L);
+
 /* Number of OpenMP threads the oracle will use. */
 int oracle_threads(void);
 

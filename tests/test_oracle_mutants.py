@@ -34,6 +34,17 @@ MUTANTS = {
                              "dS[c * d + e] += p * elem(g, b, h, i, e);"),
 }
 
+TILE_MUTANTS = {
+    "hann_not_squared": ("  return sn * sn;", "  return sn;"),
+    "hann_no_half_offset": ("((double)u + 0.5)", "((double)u)"),
+    "blend_not_normalised": ("    for (int64_t c = 0; c < C; ++c) out[p * C + c] /= wsum[p];",
+                             "    for (int64_t c = 0; c < C; ++c) out[p * C + c] /= 1.0;"),
+    "blend_ignores_halo_offset": ("          const int64_t gx = j * core[2] - halo[2] + ux;",
+                                  "          const int64_t gx = j * core[2] + ux;"),
+    "extract_wrong_row": ("          const int64_t gy = clamp64(i * core[1] - halo[1] + uy, 0, dims[1] - 1);",
+                          "          const int64_t gy = clamp64(i * core[1] + uy, 0, dims[1] - 1);"),
+}
+
 
 def phi_np(x):
     return np.where(x > 0, x + 1.0, np.exp(np.minimum(x, 0.0)))
@@ -68,6 +79,27 @@ def _pins():
     return failed
 
 
+def _tile_pins():
+    """Names of the tile-operation pins that fail for the loaded oracle."""
+    import math
+    failed = []
+    a, b = (2 - math.sqrt(2)) / 4, (2 + math.sqrt(2)) / 4
+    tiles = np.array([10.0, 20, 30, 40, 50, 60, 70, 80]).reshape(2, 1, 1, 4, 1)
+    out = oracle.tile_blend(tiles, (1, 1, 4), (1, 1, 2), (0, 0, 1)).ravel()
+    expect = [20.0, (b * 30 + a * 50) / (a + b), (a * 40 + b * 60) / (a + b), 70.0]
+    if not np.allclose(out, expect, rtol=1e-14):
+        failed.append("hand_example")
+    x = np.random.default_rng(3).standard_normal((2, 5, 7, 2))
+    for core, halo in (((1, 2, 3), (1, 1, 2)), ((2, 3, 2), (0, 2, 1))):
+        t = oracle.tile_extract(x, core, halo)
+        if not np.allclose(oracle.tile_blend(t, x.shape[:3], core, halo), x, atol=1e-13):
+            failed.append("round_trip")
+    one = oracle.tile_extract(x, (2, 5, 7), (0, 1, 1))
+    if not np.array_equal(one[0, :, 1:6, 1:8], x):
+        failed.append("extract_inner")
+    return failed
+
+
 def _build(tmp_path, text, name):
     src = tmp_path / (name + ".c")
     src.write_text(text)
@@ -99,3 +131,25 @@ def test_planted_mistake_is_caught(tmp_path, name):
     so = _build(tmp_path, text.replace(old, new), name)
     failed = _with_library(so)
     assert failed, "no pin caught the planted mistake " + name
+
+
+def _with_tile_library(path):
+    prev = oracle.use_library(path)
+    try:
+        return _tile_pins()
+    finally:
+        oracle.restore_library(prev)
+
+
+def test_unmodified_oracle_passes_tile_pins(tmp_path):
+    so = _build(tmp_path, open(SRC).read(), "pristine_tiles")
+    assert _with_tile_library(so) == []
+
+
+@pytest.mark.parametrize("name", sorted(TILE_MUTANTS))
+def test_planted_tile_mistake_is_caught(tmp_path, name):
+    old, new = TILE_MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not unique: " + name
+    so = _build(tmp_path, text.replace(old, new), name)
+    assert _with_tile_library(so), "no pin caught the planted mistake " + name
