@@ -144,6 +144,45 @@ la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,
                       size_t ws_bytes, la_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Tiles with halos and window-weighted overlap averaging.
+ *
+ * The paper's own route to global context at linear cost (Sec. III-C):
+ * the spatiotemporal token grid is cut into tiles, each extended by halos
+ * that overlap its neighbours; every tile is processed on its own (here:
+ * la_forward with the tiles as the batch); the outputs are averaged where
+ * tiles overlap, each contribution weighted by a Hann window that trusts a
+ * tile's centre more than its border.  Repeated at every diffusion step,
+ * this lets context cross tile boundaries without all-to-all attention.
+ *
+ * Geometry: the field is [T][Y][X][C] (channels contiguous).  Tile cores of
+ * (ct, cy, cx) tokens lie on a regular grid (ceil(T/ct) x ceil(Y/cy) x
+ * ceil(X/cx) tiles, row-major), each extended by halos (ht, hy, hx) with
+ * 0 <= halo <= core on every side, so a tile holds
+ * L = (ct+2ht) x (cy+2hy) x (cx+2hx) tokens, stored [tile][Lt][Ly][Lx][C].
+ *  - extract: tile values are the field at the covered positions, with
+ *    coordinates clamped into the grid at its borders.
+ *  - blend: out(p) = sum_tiles w(p) D_tile(p) / sum_tiles w(p) over the
+ *    tiles covering p, w = prod over the three dims of sin^2(pi (u+1/2)/L)
+ *    (u = coordinate within the tile); positions a tile covers outside the
+ *    grid are ignored.  Consistent tiles blend back to the field exactly.
+ * C must be a multiple of 8; the grid's y dimension limits (tiles, and
+ * T*Y rows) to 65535 each.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t dims[3];  /* T, Y, X */
+  int64_t core[3];
+  int64_t halo[3];
+  int64_t C;
+  int32_t dtype;    /* LA_BF16 or LA_FP32, field and tiles alike */
+} la_tile_desc;
+
+la_status la_tile_geometry(const la_tile_desc* desc, int64_t* n_tiles, int64_t* tile_tokens);
+la_status la_tile_extract(const la_tile_desc* desc, const void* field, void* tiles,
+                          la_stream stream);
+la_status la_tile_blend(const la_tile_desc* desc, const void* tiles, void* field,
+                        la_stream stream);
+
+/* ------------------------------------------------------------------------
  * Serving: a continuous-batching request loop for ensemble members.
  *
  * The paper generates large posterior ensembles, one member per sampler,

@@ -5,7 +5,8 @@ liblinattn.so (include/la.h); this package is its Python binding.
 """
 from ._binding import (LaError, LinearAttention, Plan, apply, backward, forward,  # noqa: F401
                        gen_fill, lib, linear_attention, profile_enable, profile_read,
-                       workspace_size)
+                       tile_blend, tile_extract, tile_geometry, tiled_attention, workspace_size)
 
 __all__ = ["forward", "apply", "backward", "LinearAttention", "linear_attention", "gen_fill",
-           "workspace_size", "lib", "LaError", "Plan", "profile_enable", "profile_read"]
+           "workspace_size", "lib", "LaError", "Plan", "profile_enable", "profile_read",
+           "tile_extract", "tile_blend", "tile_geometry", "tiled_attention"]

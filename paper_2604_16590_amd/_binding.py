@@ -306,3 +306,77 @@ class Plan:
             self.S.data_ptr(), self.z.data_ptr(), self.dout.data_ptr(), self.dq.data_ptr(),
             self.dk.data_ptr(), self.dv.data_ptr(), self.ws_b.data_ptr(), self.ws_b.numel(),
             self.stream))
+
+
+class TileDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("core", ctypes.c_int64 * 3),
+                ("halo", ctypes.c_int64 * 3), ("C", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+def _tile_desc(dims, core, halo, C, dtype):
+    T3 = ctypes.c_int64 * 3
+    return TileDesc(T3(*dims), T3(*core), T3(*halo), C, _dtype_code(dtype))
+
+
+def _tile_lib():
+    L = lib()
+    if not getattr(L, "_tiles_typed", False):
+        P = ctypes.POINTER
+        L.la_tile_geometry.argtypes = [P(TileDesc), P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.la_tile_extract.argtypes = [P(TileDesc), VP, VP, VP]
+        L.la_tile_blend.argtypes = [P(TileDesc), VP, VP, VP]
+        for n in ("la_tile_geometry", "la_tile_extract", "la_tile_blend"):
+            getattr(L, n).restype = ctypes.c_int
+        L._tiles_typed = True
+    return L
+
+
+def tile_geometry(dims, core, halo):
+    """(number of tiles, (Lt, Ly, Lx) tokens per tile)."""
+    n = [-(-int(d) // int(c)) for d, c in zip(dims, core)]
+    L = [int(c) + 2 * int(h) for c, h in zip(core, halo)]
+    return n[0] * n[1] * n[2], tuple(L)
+
+
+def tile_extract(field, core, halo):
+    """Tiles [n_tiles, Lt, Ly, Lx, C] with halos of a [T, Y, X, C] field."""
+    if field.dim() != 4 or not field.is_contiguous():
+        raise ValueError("field must be a contiguous [T, Y, X, C] tensor")
+    T, Y, X, C = field.shape
+    desc = _tile_desc((T, Y, X), core, halo, C, field.dtype)
+    n, L = tile_geometry((T, Y, X), core, halo)
+    tiles = torch.empty((n,) + L + (C,), dtype=field.dtype, device=field.device)
+    _check("la_tile_extract", _tile_lib().la_tile_extract(ctypes.byref(desc), field.data_ptr(),
+                                                          tiles.data_ptr(), _stream(field.device)))
+    return tiles
+
+
+def tile_blend(tiles, dims, core, halo):
+    """Hann-weighted overlap average of tiles back onto a [T, Y, X, C] field."""
+    if not tiles.is_contiguous():
+        raise ValueError("tiles must be contiguous")
+    C = tiles.shape[-1]
+    desc = _tile_desc(dims, core, halo, C, tiles.dtype)
+    n, L = tile_geometry(dims, core, halo)
+    if tiles.shape != (n,) + L + (C,):
+        raise ValueError("tiles must be [n_tiles, Lt, Ly, Lx, C] = %s" % (((n,) + L + (C,)),))
+    out = torch.empty(tuple(dims) + (C,), dtype=tiles.dtype, device=tiles.device)
+    _check("la_tile_blend", _tile_lib().la_tile_blend(ctypes.byref(desc), tiles.data_ptr(),
+                                                      out.data_ptr(), _stream(tiles.device)))
+    return out
+
+
+def tiled_attention(q, k, v, core, halo):
+    """The paper's tiled global attention step: split the [T, Y, X, H*d]
+    token fields into overlapping tiles, run linear attention inside every
+    tile (tiles as the batch, heads packed in the channels), and blend the
+    tile outputs with Hann weights.  q, k, v: [T, Y, X, H, d] tensors."""
+    T, Y, X, H, d = q.shape
+    flat = lambda t: t.reshape(T, Y, X, H * d)
+    tq, tk, tv = (tile_extract(flat(t), core, halo) for t in (q, k, v))
+    n = tq.shape[0]
+    N = tq.shape[1] * tq.shape[2] * tq.shape[3]
+    view = lambda t: t.view(n, N, H, d).permute(0, 2, 1, 3)  # [B=tiles, H, N, d] view
+    to = torch.empty_like(tq)
+    forward(view(tq), view(tk), view(tv), out=view(to))
+    return tile_blend(to, (T, Y, X), core, halo).view(T, Y, X, H, d)

@@ -114,3 +114,19 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError):
         B.lib()
+
+
+def test_tile_geometry_and_validation():
+    L = B._tile_lib()
+    n, t = ctypes.c_int64(0), ctypes.c_int64(0)
+    d = B._tile_desc((3, 10, 7), (1, 3, 2), (1, 3, 2), 16, B.torch.bfloat16)
+    assert L.la_tile_geometry(ctypes.byref(d), ctypes.byref(n), ctypes.byref(t)) == 0
+    assert n.value == 3 * 4 * 4 and t.value == 3 * 9 * 6
+    assert (n.value, (3, 9, 6)) == B.tile_geometry((3, 10, 7), (1, 3, 2), (1, 3, 2))
+    for dims, core, halo, C in (((3, 10, 7), (1, 3, 2), (2, 0, 0), 16),   # halo > core
+                                ((3, 10, 7), (1, 3, 2), (0, 0, 0), 12),   # C not a multiple of 8
+                                ((0, 10, 7), (1, 3, 2), (0, 0, 0), 16)):
+        bad = B._tile_desc(dims, core, halo, C, B.torch.float32)
+        assert L.la_tile_geometry(ctypes.byref(bad), ctypes.byref(n), ctypes.byref(t)) == 1
+    fake = 1 << 20
+    assert L.la_tile_extract(ctypes.byref(d), fake + 8, fake, None) == 1

@@ -1,0 +1,79 @@
+"""Tiles with halos and Hann-weighted overlap averaging on the GPU against
+the oracle, and the tiled attention step composed from them."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_16590_amd as la
+from gpu_util import TOL, as64, make_inputs, normwise, require_gpu, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = [((1, 32, 64), (1, 16, 16), (0, 4, 4)), ((4, 9, 13), (2, 4, 5), (1, 2, 2)),
+         ((2, 8, 8), (2, 8, 8), (0, 0, 0)), ((3, 10, 7), (1, 3, 2), (1, 3, 2))]
+
+
+def field(dims, C, dtype, seed):
+    T, Y, X = dims
+    (x,) = make_inputs((1, 1, T * Y * X, C), dtype, seed, streams=(0,))
+    return x.reshape(T, Y, X, C)
+
+
+@pytest.mark.parametrize("dims,core,halo", GEOMS)
+@pytest.mark.parametrize("dtype", ["bf16", "fp32"])
+def test_extract_and_blend_match_oracle(dims, core, halo, dtype):
+    dev = require_gpu()
+    x = field(dims, 16, dtype, 41)
+    tx = to_device(x, dev)
+    tiles = la.tile_extract(tx, core, halo)
+    torch.cuda.synchronize()
+    ref_tiles = oracle.tile_extract(as64(x), core, halo)
+    np.testing.assert_array_equal(as64(tiles), ref_tiles)  # a gather: bit-exact
+    # blend arbitrary (inconsistent) tiles
+    n, L = la.tile_geometry(dims, core, halo)
+    (raw,) = make_inputs((1, 1, n * L[0] * L[1] * L[2], 16), dtype, 42, streams=(1,))
+    raw = raw.reshape((n,) + L + (16,))
+    out = la.tile_blend(to_device(raw, dev), dims, core, halo)
+    torch.cuda.synchronize()
+    ref = oracle.tile_blend(as64(raw), dims, core, halo)
+    err = normwise(as64(out)[None, None], ref[None, None])
+    assert err < (4e-3 if dtype == "bf16" else 1e-6), err
+    # consistent tiles blend back to the field
+    back = la.tile_blend(tiles, dims, core, halo)
+    torch.cuda.synchronize()
+    assert normwise(as64(back)[None, None], as64(x)[None, None]) < (4e-3 if dtype == "bf16" else 1e-6)
+
+
+def test_tiled_attention_matches_oracle_composition():
+    dev = require_gpu()
+    T, Y, X, H, d = 2, 16, 24, 2, 32
+    core, halo = (1, 8, 8), (0, 2, 3)
+    q, k, v = (field((T, Y, X), H * d, "bf16", s) for s in (43, 44, 45))
+    tq, tk, tv = (to_device(a, dev).view(T, Y, X, H, d) for a in (q, k, v))
+    out = la.tiled_attention(tq, tk, tv, core, halo)
+    torch.cuda.synchronize()
+    # oracle: the same composition, in FP64
+    n, L = la.tile_geometry((T, Y, X), core, halo)
+    N = L[0] * L[1] * L[2]
+    tiles = [oracle.tile_extract(as64(a), core, halo).reshape(n, N, H, d).transpose(0, 2, 1, 3)
+             for a in (q, k, v)]
+    o_tiles = oracle.forward(*(np.ascontiguousarray(t) for t in tiles))
+    o_tiles = o_tiles.transpose(0, 2, 1, 3).reshape((n,) + L + (H * d,))
+    ref = oracle.tile_blend(o_tiles, (T, Y, X), core, halo)
+    err = normwise(as64(out).reshape(1, 1, -1), ref.reshape(1, 1, -1))
+    print("tiled attention normwise", err)
+    assert err < TOL["bf16"]
+
+
+def test_one_tile_is_global_attention():
+    dev = require_gpu()
+    T, Y, X, H, d = 2, 8, 16, 2, 64
+    q, k, v = (field((T, Y, X), H * d, "fp32", s) for s in (46, 47, 48))
+    tq, tk, tv = (to_device(a, dev).view(T, Y, X, H, d) for a in (q, k, v))
+    out = la.tiled_attention(tq, tk, tv, (T, Y, X), (0, 0, 0))
+    glob = la.forward(*(t.reshape(1, T * Y * X, H, d).permute(0, 2, 1, 3) for t in (tq, tk, tv)))
+    torch.cuda.synchronize()
+    a = out.reshape(T * Y * X, H, d)
+    b = glob[0].permute(1, 0, 2)
+    assert torch.allclose(a, b, rtol=1e-6, atol=1e-7)
