@@ -472,15 +472,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
+template <int DT, int D, int MODE>
+static void launch_summary_t(const void* k, const void* v, int64_t sb, int64_t sh, int64_t sn,
+                             int64_t BH, int64_t H, int64_t N, int P, int Tw,
+                             const float2* stash, float* part, hipStream_t stream) {
+  using C = SummaryCfg<DT, D, MODE>;
+  // block geometry comes from the kernel's own configuration: SPLIT waves
+  // share one partial, or four waves take one partial each
+  static_assert(C::THREADS == 64 * (C::SPLIT > 1 ? C::SPLIT : 4), "block shape");
+  static_assert(C::SPLIT == 1 || C::PPB == 1, "split blocks hold one partial");
+  const dim3 grid((unsigned)((P + C::PPB - 1) / C::PPB), (unsigned)BH);
+  summary_kernel<DT, D, MODE><<<grid, C::THREADS, 0, stream>>>(k, v, sb, sh, sn, (int)H, N, P, Tw,
+                                                               stash, part);
+}
+
 template <int D>
 static void launch_summary_d(int mode, int dt, const void* k, const void* v, int64_t sb,
                              int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
                              int Tw, const float2* stash, float* part, hipStream_t stream) {
-  constexpr int PPB = D >= 128 ? 2 : 4;  // SummaryCfg<*, D>::PPB
-  dim3 grid((P + PPB - 1) / PPB, (unsigned)(B * H));
   ProfScope prof(mode == MODE_FWD ? "summary_fwd" : "summary_bwd", stream);
+  const int64_t BH = B * H;
 #define LA_SUM(DTI, M) \
-  summary_kernel<DTI, D, M><<<grid, 256, 0, stream>>>(k, v, sb, sh, sn, (int)H, N, P, Tw, stash, part)
+  launch_summary_t<DTI, D, M>(k, v, sb, sh, sn, BH, H, N, P, Tw, stash, part, stream)
   if (mode == MODE_FWD) {
     if (dt == DT_BF16) LA_SUM(DT_BF16, MODE_FWD); else LA_SUM(DT_FP32, MODE_FWD);
   } else {
