@@ -32,7 +32,7 @@ struct SummaryCfg {
   // waves sharing one token range; each owns F/SPLIT rows of S tiles and
   // loads F/SPLIT of the value features, whose matrix-core operands it
   // shares with the others through LDS, so K and V are each read once
-  static constexpr int SPLIT = D >= 128 ? (MODE == MODE_BWD ? 4 : 2) : 1;
+  static constexpr int SPLIT = D >= 128 ? 2 : 1;
   static constexpr int FR = F / SPLIT;             // S tile rows (key features) per wave
   static constexpr int FC = F / SPLIT;             // value features loaded per wave
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
@@ -54,16 +54,23 @@ struct SummaryRegs {
   using C = SummaryCfg<DT, D, MODE>;
   uint32_t kw[C::R][C::KW];
   uint32_t vw[C::R][C::VW];
-  float2 tok[C::R];
+  // backward mode: lane (g, m), m < R, holds the pair of token R*g + m;
+  // the step broadcasts it across the lane group when it is needed
+  float2 tok;
 };
+
+// The pair of token R*g + r of this lane's group (lane 16g + r holds it).
+__device__ __forceinline__ float2 group_bcast(float2 v, int r) {
+  return float2{__shfl(v.x, r, 16), __shfl(v.y, r, 16)};
+}
 
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
 // they add exactly nothing to S or z and the step itself needs no masks.
 // In the backward mode the per-token pair (1/den, -(dO . O)) is loaded too.
 template <int DT, int D, int MODE>
 __device__ __forceinline__ void summary_load(const char* kp, const char* vp, const float2* stash,
-                                             int64_t row_bytes, int64_t t0, int g, int64_t t_end,
-                                             SummaryRegs<DT, D, MODE>& x) {
+                                             int64_t row_bytes, int64_t t0, int g, int m,
+                                             int64_t t_end, SummaryRegs<DT, D, MODE>& x) {
   using C = SummaryCfg<DT, D, MODE>;
   const uint32_t neg_inf = DT == DT_BF16 ? 0xff80ff80u : 0xff800000u;
   const bool partial = t0 + C::STEP > t_end;
@@ -73,14 +80,16 @@ __device__ __forceinline__ void summary_load(const char* kp, const char* vp, con
     if (!partial || t < t_end) {
       load_words<C::KB>(kp + t * row_bytes, x.kw[r]);
       load_words<C::VB>(vp + t * row_bytes, x.vw[r]);
-      if constexpr (MODE == MODE_BWD) x.tok[r] = stash[t];
     } else {
 #pragma unroll
       for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
 #pragma unroll
       for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
-      if constexpr (MODE == MODE_BWD) x.tok[r] = float2{0.f, 0.f};
     }
+  }
+  if constexpr (MODE == MODE_BWD) {
+    const int64_t t = t0 + C::R * g + m;
+    x.tok = (m < C::R && t < t_end) ? stash[t] : float2{0.f, 0.f};
   }
 }
 
@@ -117,30 +126,37 @@ __device__ __forceinline__ void summary_step(const SummaryRegs<DT, D, MODE>& x, 
         for (int pp = 0; pp < 4; ++pp) xch[((part * FC + jj) * 4 + pp) * 64 + lane] = own[jj][pp];
       __syncthreads();
     }
-    // key operands of this wave's rows
-    bf16x8 ak[FR];
+    // key operands of this wave's rows (token pair outermost, so only
+    // one pair of per-token scalars is live in the backward mode)
+    uint32_t pk[FR][4];
 #pragma unroll
-    for (int i = 0; i < FR; ++i) {
-      uint32_t pk[4];
+    for (int pp = 0; pp < 4; ++pp) {
+      float2 t0 = float2{1.f, 0.f}, t1 = float2{1.f, 0.f};
+      if constexpr (MODE == MODE_BWD) {
+        t0 = group_bcast(x.tok, 2 * pp);
+        t1 = group_bcast(x.tok, 2 * pp + 1);
+      }
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp) {
+      for (int i = 0; i < FR; ++i) {
         float p0 = phi<DT>(word_elem<DT>(x.kw[2 * pp], i));
         float p1 = phi<DT>(word_elem<DT>(x.kw[2 * pp + 1], i));
         if constexpr (MODE == MODE_BWD) {
-          p0 *= x.tok[2 * pp].x;
-          p1 *= x.tok[2 * pp + 1].x;
+          p0 *= t0.x;
+          p1 *= t1.x;
         }
-        pk[pp] = pack_bf16(p0, p1);
+        pk[i][pp] = pack_bf16(p0, p1);
         if constexpr (MODE == MODE_FWD) {
           // normaliser from the same rounded phi values that feed S
-          zacc[i] = add_bf16_pair(zacc[i], pk[pp]);
+          zacc[i] = add_bf16_pair(zacc[i], pk[i][pp]);
         } else {
-          zacc[i] = fmaf(x.tok[2 * pp].y, bf16lo(pk[pp]), zacc[i]);
-          zacc[i] = fmaf(x.tok[2 * pp + 1].y, bf16hi(pk[pp]), zacc[i]);
+          zacc[i] = fmaf(t0.y, bf16lo(pk[i][pp]), zacc[i]);
+          zacc[i] = fmaf(t1.y, bf16hi(pk[i][pp]), zacc[i]);
         }
       }
-      ak[i] = as_bf16x8(u32x4{pk[0], pk[1], pk[2], pk[3]});
     }
+    bf16x8 ak[FR];
+#pragma unroll
+    for (int i = 0; i < FR; ++i) ak[i] = as_bf16x8(u32x4{pk[i][0], pk[i][1], pk[i][2], pk[i][3]});
 #pragma unroll
     for (int j = 0; j < F; ++j) {
       bf16x8 bv;
@@ -164,14 +180,16 @@ __device__ __forceinline__ void summary_step(const SummaryRegs<DT, D, MODE>& x, 
 #pragma unroll
     for (int r = 0; r < C::R; ++r) {
       float pk[FR];
+      float2 tr = float2{1.f, 0.f};
+      if constexpr (MODE == MODE_BWD) tr = group_bcast(x.tok, r);
 #pragma unroll
       for (int i = 0; i < FR; ++i) {
         pk[i] = phi<DT>(word_elem<DT>(x.kw[r], i));
         if constexpr (MODE == MODE_FWD) {
           zacc[i] += pk[i];
         } else {
-          pk[i] *= x.tok[r].x;
-          zacc[i] = fmaf(x.tok[r].y, pk[i], zacc[i]);
+          pk[i] *= tr.x;
+          zacc[i] = fmaf(tr.y, pk[i], zacc[i]);
         }
       }
 #pragma unroll
@@ -227,11 +245,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   __shared__ uint32_t xch[2 * C::XW];
   int buf = 0;
   SummaryRegs<DT, D, MODE> cur;
-  summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t_begin, g, t_end, cur);
+  summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t_begin, g, m, t_end, cur);
   for (int64_t t0 = t_begin; t0 < t_end; t0 += C::STEP) {
     SummaryRegs<DT, D, MODE> nxt;
     const bool more = t0 + C::STEP < t_end;
-    if (more) summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0 + C::STEP, g, t_end, nxt);
+    if (more) summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0 + C::STEP, g, m, t_end, nxt);
     summary_step<DT, D, MODE>(cur, half, lane, xch + buf * C::XW, acc, zacc);
     buf ^= 1;
     if (more) cur = nxt;

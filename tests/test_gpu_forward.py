@@ -171,11 +171,22 @@ def test_generator_matches_host_definition():
             host = inputs.generate(inputs.GenSpec(seed=1234, stream=2, std=std, grid=grid,
                                                   tensor_id=2), shape, dtype)
             dv, hv = as64(x), inputs.as_float64(host)
-            # FP32 transcendentals of the two math libraries may differ in
-            # the last bits: within a few fp32 ulps, or one bf16 rounding
-            tol = 2.0 ** -7 if dtype == "bf16" else 2.0 ** -19
-            scale = np.maximum(np.abs(hv), 1e-3)
-            assert np.all(np.abs(dv - hv) <= tol * scale * 1.01)
+            # The generator is built without contraction, so both sides round
+            # the same FP32 operations; only the transcendentals of the two
+            # math libraries may differ in the last bits (a few ulps of a
+            # grid phase of up to ~45 rad, i.e. ~1e-6 absolute in the sine).
+            # Allowed: one rounding of the stored type relative to the value,
+            # plus that absolute term.
+            rel = 2.0 ** -7 if dtype == "bf16" else 2.0 ** -19
+            absf = (2.0 ** -18 if grid else 2.0 ** -20)
+            lim = rel * np.abs(hv) * 1.01 + absf
+            bad = np.abs(dv - hv) > lim
+            if bad.any():
+                worst = np.argsort(((np.abs(dv - hv) - lim)).ravel())[-5:]
+                for w in worst:
+                    print("gen mismatch", dtype, grid, np.unravel_index(w, shape),
+                          dv.ravel()[w], hv.ravel()[w], flush=True)
+            assert not bad.any(), (dtype, grid, int(bad.sum()))
             assert np.mean(dv == hv) > (0.97 if dtype == "bf16" else 0.5)
 
 
