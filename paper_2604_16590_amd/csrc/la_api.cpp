@@ -44,6 +44,8 @@ la_status check_desc(const la_attn_desc* d) {
       if ((s[t][i] * es[t]) % 16 != 0) return LA_ERR_INVALID_ARG;
     }
     if (s[t][2] < d->d) return LA_ERR_INVALID_ARG;
+    // kernels address 32 consecutive token rows with 32-bit lane offsets
+    if (s[t][2] * es[t] > (int64_t(1) << 24)) return LA_ERR_UNSUPPORTED;
   }
   return LA_OK;
 }

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   stage_image(simg, (const u32x4*)((const char*)img + (int64_t)bh * IC::head_bytes(DT) +
                                    IC::img_bytes(DT)),
               IMG_WORDS, false);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
   double zr[Q4];
 #pragma unroll
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const u32x4* head = (const u32x4*)((const char*)dimg + (int64_t)bh * IC::head_bytes(DT));
   if (DO_V) stage_image(timg, head, ONE, DT == DT_BF16);
   if (DO_K) stage_image(nimg, head + IC::img_bytes(DT) / 16, ONE, DT == DT_BF16);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
   double dzr[DO_K ? Q4 : 1];
   if constexpr (DO_K) {

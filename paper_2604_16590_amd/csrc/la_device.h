@@ -70,6 +70,12 @@ __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4& w) {
   return __builtin_bit_cast(bf16x8, w);
 }
 
+// Index of the calling wave within its workgroup, as a wave-uniform value
+// (scalar register), so that everything derived from it stays scalar.
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 // Butterfly sum over the four lane groups (lanes m, m+16, m+32, m+48).
 __device__ __forceinline__ double sum_groups(double x) {
   x += __shfl_xor(x, 16);
@@ -101,6 +107,30 @@ __device__ __forceinline__ void load_words(const void* p, uint32_t* w) {
   } else {
     static_assert(BYTES == 2, "unsupported width");
     w[0] = *(const uint16_t*)p;
+  }
+}
+
+// The same with the non-temporal hint: for data streamed exactly once (the
+// summary's token ranges), which then does not displace reused lines in
+// the caches; on gfx950 such read-only streams run measurably closer to
+// the HBM peak.
+template <int BYTES>
+__device__ __forceinline__ void load_words_nt(const void* p, uint32_t* w) {
+  if constexpr (BYTES >= 16) {
+    static_assert(BYTES % 16 == 0, "unsupported width");
+#pragma unroll
+    for (int i = 0; i < BYTES / 16; ++i) {
+      const u32x4 a = __builtin_nontemporal_load((const u32x4*)p + i);
+      w[4 * i] = a.x; w[4 * i + 1] = a.y; w[4 * i + 2] = a.z; w[4 * i + 3] = a.w;
+    }
+  } else if constexpr (BYTES == 8) {
+    const u32x2 a = __builtin_nontemporal_load((const u32x2*)p);
+    w[0] = a.x; w[1] = a.y;
+  } else if constexpr (BYTES == 4) {
+    w[0] = __builtin_nontemporal_load((const uint32_t*)p);
+  } else {
+    static_assert(BYTES == 2, "unsupported width");
+    w[0] = __builtin_nontemporal_load((const uint16_t*)p);
   }
 }
 

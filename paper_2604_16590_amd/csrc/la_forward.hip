@@ -31,8 +31,12 @@ struct SummaryCfg {
   static constexpr int F = D / 16;                 // features per lane (S tile grid is F x F)
   // waves sharing one token range; each owns F/SPLIT rows of S tiles and
   // loads F/SPLIT of the value features, whose matrix-core operands it
-  // shares with the others through LDS, so K and V are each read once
-  static constexpr int SPLIT = D >= 128 ? 2 : 1;
+  // shares with the others through LDS, so K and V are each read once.
+  // bf16 at d = 128 keeps the whole S (256 accumulator registers) in one
+  // wave, in the accumulation registers, at one wave per SIMD; fp32 there
+  // needs more registers for its operands and splits in two.
+  static constexpr int SPLIT = D >= 128 && DT == DT_FP32 ? 2 : 1;
+  static constexpr int WAVES_PER_SIMD = D >= 128 && DT == DT_BF16 ? 1 : 2;
   static constexpr int FR = F / SPLIT;             // S tile rows (key features) per wave
   static constexpr int FC = F / SPLIT;             // value features loaded per wave
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
@@ -67,24 +71,37 @@ __device__ __forceinline__ float2 group_bcast(float2 v, int r) {
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
 // they add exactly nothing to S or z and the step itself needs no masks.
 // In the backward mode the per-token pair (1/den, -(dO . O)) is loaded too.
+// Addresses split into a wave-uniform part (head + (t0 + r) rows, scalar
+// registers) and a loop-invariant 32-bit lane offset (koff, voff: the lane
+// group's first row and the lane's feature run), so the loads need no
+// per-lane address arithmetic.
 template <int DT, int D, int MODE>
-__device__ __forceinline__ void summary_load(const char* kp, const char* vp, const float2* stash,
+__device__ __forceinline__ void summary_load(const char* kh, const char* vh, uint32_t koff,
+                                             uint32_t voff, const float2* stash,
                                              int64_t row_bytes, int64_t t0, int g, int m,
                                              int64_t t_end, SummaryRegs<DT, D, MODE>& x) {
   using C = SummaryCfg<DT, D, MODE>;
   const uint32_t neg_inf = DT == DT_BF16 ? 0xff80ff80u : 0xff800000u;
-  const bool partial = t0 + C::STEP > t_end;
+  if (t0 + C::STEP <= t_end) {
 #pragma unroll
-  for (int r = 0; r < C::R; ++r) {
-    const int64_t t = t0 + C::R * g + r;
-    if (!partial || t < t_end) {
-      load_words<C::KB>(kp + t * row_bytes, x.kw[r]);
-      load_words<C::VB>(vp + t * row_bytes, x.vw[r]);
-    } else {
+    for (int r = 0; r < C::R; ++r) {
+      const int64_t ur = (t0 + r) * row_bytes;
+      load_words_nt<C::KB>(kh + ur + koff, x.kw[r]);
+      load_words_nt<C::VB>(vh + ur + voff, x.vw[r]);
+    }
+  } else {
 #pragma unroll
-      for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
+    for (int r = 0; r < C::R; ++r) {
+      const int64_t ur = (t0 + r) * row_bytes;
+      if (t0 + C::R * g + r < t_end) {
+        load_words_nt<C::KB>(kh + ur + koff, x.kw[r]);
+        load_words_nt<C::VB>(vh + ur + voff, x.vw[r]);
+      } else {
 #pragma unroll
-      for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
+        for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
+#pragma unroll
+        for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
+      }
     }
   }
   if constexpr (MODE == MODE_BWD) {
@@ -207,14 +224,14 @@ __device__ __forceinline__ void summary_step(const SummaryRegs<DT, D, MODE>& x, 
 // a block takes its own partial; otherwise the block's SPLIT waves share
 // partial x, wave w owning S tile rows [FR*w, +FR).
 template <int DT, int D, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void summary_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SummaryCfg<DT, D, MODE>::WAVES_PER_SIMD))) void summary_kernel(
     const void* __restrict__ k, const void* __restrict__ v, int64_t sb,
     int64_t sh, int64_t sn, int H, int64_t N, int P, int Tw,
     const float2* __restrict__ stash, float* __restrict__ part) {
   using C = SummaryCfg<DT, D, MODE>;
   constexpr int F = C::F, FR = C::FR;
   constexpr int E = D * D + D;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, m = lane & 15;
   const int p = C::SPLIT > 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + wave;
   const int half = C::SPLIT > 1 ? wave : 0;
@@ -225,10 +242,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const int64_t t_end = min(N, t_begin + (int64_t)Tw);
   const int64_t head = (b * sb + h * sh) * C::ES;
   // lane m reads key features [F*m + FR*half, +FR) and value features
-  // [F*m + FC*half, +FC)
-  const char* kp = (const char*)k + head + (int64_t)(F * m + FR * half) * C::ES;
-  const char* vp = (const char*)v + head + (int64_t)(F * m + C::FC * half) * C::ES;
+  // [F*m + FC*half, +FC) of rows R*g + r (the host bounds 32 rows of the
+  // token stride to 2^24 bytes, so the lane offsets fit 32 bits)
   const int64_t row_bytes = sn * C::ES;
+  const char* kh = (const char*)k + head;
+  const char* vh = (const char*)v + head;
+  const uint32_t roff = (uint32_t)(C::R * g) * (uint32_t)row_bytes;
+  const uint32_t koff = roff + (uint32_t)((F * m + FR * half) * C::ES);
+  const uint32_t voff = roff + (uint32_t)((F * m + C::FC * half) * C::ES);
   const float2* tstash = MODE == MODE_BWD ? stash + (int64_t)bh * N : nullptr;
 
   f32x4 acc[FR][F];
@@ -243,16 +264,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   // double-buffered exchange: one barrier per step suffices, because a
   // buffer is rewritten only after the barrier of the step in between
   __shared__ uint32_t xch[2 * C::XW];
-  int buf = 0;
-  SummaryRegs<DT, D, MODE> cur;
-  summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t_begin, g, m, t_end, cur);
-  for (int64_t t0 = t_begin; t0 < t_end; t0 += C::STEP) {
-    SummaryRegs<DT, D, MODE> nxt;
-    const bool more = t0 + C::STEP < t_end;
-    if (more) summary_load<DT, D, MODE>(kp, vp, tstash, row_bytes, t0 + C::STEP, g, m, t_end, nxt);
-    summary_step<DT, D, MODE>(cur, half, lane, xch + buf * C::XW, acc, zacc);
-    buf ^= 1;
-    if (more) cur = nxt;
+  // two register sets in turn: while one step computes, the next one's
+  // loads are in flight in the other set (no copies between them)
+  SummaryRegs<DT, D, MODE> ra, rb;
+  auto load = [&](int64_t t0, SummaryRegs<DT, D, MODE>& x) {
+    summary_load<DT, D, MODE>(kh, vh, koff, voff, tstash, row_bytes, t0, g, m, t_end, x);
+  };
+  int64_t t0 = t_begin;
+  load(t0, ra);
+  while (true) {
+    const int64_t t1 = t0 + C::STEP;
+    if (t1 < t_end) load(t1, rb);
+    summary_step<DT, D, MODE>(ra, half, lane, xch, acc, zacc);
+    if (t1 >= t_end) break;
+    const int64_t t2 = t1 + C::STEP;
+    if (t2 < t_end) load(t2, ra);
+    summary_step<DT, D, MODE>(rb, half, lane, xch + C::XW, acc, zacc);
+    if (t2 >= t_end) break;
+    t0 = t2;
   }
 
   // this wave's share of the partial: S tiles in lane order, then z
@@ -345,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     const u32x4* src = (const u32x4*)((const char*)img + (int64_t)bh * IC::head_bytes(DT));
     for (int w = threadIdx.x; w < IMG_WORDS; w += 256) simg[w] = src[w];
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
   double zr[Q4];
 #pragma unroll
