@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   using IC = ImageCfg<D>;
   constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
+  constexpr int IMG_WORDS = IC::mat_bytes(DT) / 16;  // the N image
   __shared__ u32x4 simg[IMG_WORDS];
 
   const int bh = blockIdx.y;
@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   using IC = ImageCfg<D>;
   constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int ONE = DT == DT_BF16 ? IC::img_bytes(DT) / 32 : IC::img_bytes(DT) / 16;
+  // matrix tiles only (the z tile is not needed here); bf16: hi parts only
+  constexpr int ONE = DT == DT_BF16 ? IC::mat_bytes(DT) / 32 : IC::mat_bytes(DT) / 16;
   constexpr bool DO_V = WHICH & 1, DO_K = WHICH & 2;
   __shared__ u32x4 simg[(DO_V ? ONE : 0) + (DO_K ? ONE : 0)];
   u32x4* timg = simg;
@@ -457,7 +458,7 @@ static void launch_rows(const BwdArgs& a) {
 
 template <int D>
 static hipError_t launch_backward_d(const BwdArgs& a) {
-  hipError_t e = launch_images(a.S64, a.img, a.in_dt, a.B * a.H, D, a.stream);
+  hipError_t e = launch_images(a.S64, a.z64, a.img, a.in_dt, a.B * a.H, D, a.stream);
   if (e != hipSuccess) return e;
   if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) launch_rows<DT_BF16, DT_BF16, D>(a);
   else if (a.in_dt == DT_BF16) launch_rows<DT_BF16, DT_FP32, D>(a);

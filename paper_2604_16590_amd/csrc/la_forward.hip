@@ -326,45 +326,61 @@ __global__ __launch_bounds__(256) void combine_kernel(
     write_images<D>(img, img_dt, bh, c, e, s);
   } else {
     v64[(int64_t)bh * D + (u - D * D)] = s;
+    write_z_tile<D>(img, img_dt, bh, u - D * D, s);
   }
 }
 
-// Images from a dense FP64 matrix (used when S comes from the caller).
+// Images from a dense FP64 matrix and vector (used when S, z come from the
+// caller).
 template <int D>
 __global__ __launch_bounds__(256) void image_kernel(const double* __restrict__ M64,
+                                                    const double* __restrict__ v64,
                                                     void* __restrict__ img, int img_dt) {
   const int bh = blockIdx.y;
   const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= D * D) return;
-  write_images<D>(img, img_dt, bh, u / D, u % D, M64[(int64_t)bh * D * D + u]);
+  if (u < D * D) {
+    write_images<D>(img, img_dt, bh, u / D, u % D, M64[(int64_t)bh * D * D + u]);
+  } else if (u < D * D + D) {
+    write_z_tile<D>(img, img_dt, bh, u - D * D, v64[(int64_t)bh * D + (u - D * D)]);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Apply: O^T = S^T phi(Q)^T per 16-token tile.  Lane (g, n) holds token n
 // and query features [g*Q4, g*Q4 + Q4) (Q4 = d/4), read as one contiguous
 // run; the matrix-core result puts value features [g*Q4, g*Q4 + Q4) of the
-// same token in the same lane, so the normaliser, the FP64 division and the
-// store all stay in-lane.  The S^T operands (bf16 hi + lo parts, or fp32)
-// sit in LDS for the whole workgroup.
+// same token in the same lane.  The normaliser den = phi(q) . z comes from
+// the same matrix-core pass (the image's z tile: every output row of it is
+// den of the lane's token), so the FP64 division and the store stay
+// in-lane.  The S^T operands (bf16 hi + lo parts, or fp32) sit in LDS for
+// the whole workgroup.
 // ---------------------------------------------------------------------------
+template <int DT, int D>
+struct ApplyCfg {
+  // 16-token tiles per step; every LDS operand read feeds TT matrix-core
+  // ops (fp32 at d = 128: one, for registers)
+  static constexpr int TT = DT == DT_FP32 && D >= 128 ? 1 : 2;
+  static constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  static constexpr int QB = D / 4 * ES;             // bytes of a lane's query run
+  static constexpr int QW = QB >= 4 ? QB / 4 : 1;
+};
+
 template <int DT, int OT, int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void apply_kernel(
     const void* __restrict__ q, int64_t sb, int64_t sh, int64_t sn,
     void* __restrict__ o, int64_t osb, int64_t osh, int64_t osn, int H,
-    int64_t N, int Ta, const void* __restrict__ img,
-    const double* __restrict__ z64) {
+    int64_t N, int Ta, const void* __restrict__ img) {
   using IC = ImageCfg<D>;
+  using AC = ApplyCfg<DT, D>;
   constexpr int Q4 = D / 4;
   constexpr int NT = D / 16;
-  constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  constexpr int ES = AC::ES;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int QB = Q4 * ES;                 // bytes of a lane's query run
-  constexpr int QW = QB >= 4 ? QB / 4 : 1;
+  constexpr int QB = AC::QB, QW = AC::QW;
   constexpr int OB = Q4 * OES;
   constexpr int OW = OB >= 4 ? OB / 4 : 1;
   constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
-  // 16-token tiles per LDS operand read (fp32 at d = 128: one, for registers)
-  constexpr int TT = DT == DT_FP32 && D >= 128 ? 1 : 2;
+  constexpr int TT = AC::TT;
   __shared__ u32x4 simg[IMG_WORDS];
 
   const int bh = blockIdx.y;
@@ -376,54 +392,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   }
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
-  double zr[Q4];
-#pragma unroll
-  for (int c = 0; c < Q4; ++c) zr[c] = z64[(int64_t)bh * D + g * Q4 + c];
   __syncthreads();
 
   const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
   const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
-  const char* qbase = (const char*)q + (b * sb + h * sh) * ES + (int64_t)g * QB;
-  char* obase = (char*)o + (b * osb + h * osh) * OES + (int64_t)g * OB;
+  // wave-uniform head pointers plus loop-invariant 32-bit lane offsets
+  // (token n of the tile, lane group g's feature run)
+  const int64_t row_bytes = sn * ES, orow_bytes = osn * OES;
+  const char* qh = (const char*)q + (b * sb + h * sh) * ES;
+  char* oh = (char*)o + (b * osb + h * osh) * OES;
+  const uint32_t qoff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * QB);
+  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OB);
 
-  auto load_q = [&](int64_t t0, uint32_t (&qw)[TT][QW]) {
+  typedef uint32_t QRegs[TT][QW];
+  auto load_q = [&](int64_t t0, QRegs& qw) {
+    if (t0 + 16 * TT <= wg_end) {
 #pragma unroll
-    for (int tt = 0; tt < TT; ++tt) {
-      const int64_t t = t0 + 16 * tt + n;
-      if (t < wg_end) {
-        load_words<QB>(qbase + t * sn * ES, qw[tt]);
-      } else {
+      for (int tt = 0; tt < TT; ++tt) load_words<QB>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+    } else {
 #pragma unroll
-        for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
+      for (int tt = 0; tt < TT; ++tt) {
+        if (t0 + 16 * tt + n < wg_end) {
+          load_words<QB>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+        } else {
+#pragma unroll
+          for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
+        }
       }
     }
   };
-  // prefetch one step ahead where the registers allow it
-  constexpr bool PF = true;
-  uint32_t qcur[TT][QW];
-  const int64_t first = wg_begin + 16 * TT * wave;
-  if (first < wg_end) load_q(first, qcur);
-  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
-    if constexpr (!PF) {
-      if (t0 != first) load_q(t0, qcur);  // no prefetch: this step's load
-    }
-    // next step's queries are in flight while this step computes
-    uint32_t qw[TT][QW], qnext[TT][QW];
-    const bool more = PF && t0 + 16 * TT * 4 < wg_end;
-    if (more) load_q(t0 + 16 * TT * 4, qnext);
+
+  auto compute = [&](int64_t t0, const QRegs& qw) {
+    // phi(q) as matrix-core operands; acc[tt][NT] is the z tile (den)
+    f32x4 acc[TT][NT + 1];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-      for (int w = 0; w < QW; ++w) qw[tt][w] = qcur[tt][w];
-    // phi(q), the FP64 normaliser, and the matrix-core operands
-    double den[TT];
-    f32x4 acc[TT][NT];
-#pragma unroll
-    for (int tt = 0; tt < TT; ++tt) {
-      den[tt] = 0.0;
-#pragma unroll
-      for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+      for (int i = 0; i <= NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (DT == DT_BF16) {
       constexpr int NS = IC::NS;
       bf16x8 bq[TT][NS];
@@ -439,8 +444,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
               const float p0 = phi<DT>(word_elem<DT>(qw[tt], c0));
               const float p1 = phi<DT>(word_elem<DT>(qw[tt], c0 + 1));
               w[pp] = pack_bf16(p0, p1);
-              den[tt] = fma((double)bf16lo(w[pp]), zr[c0], den[tt]);
-              den[tt] = fma((double)bf16hi(w[pp]), zr[c0 + 1], den[tt]);
             } else {
               w[pp] = 0;
             }
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
           bq[tt][s] = as_bf16x8(w);
         }
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
+      for (int i = 0; i <= NT; ++i)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const bf16x8 hi = as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]);
@@ -466,12 +469,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-        for (int c = 0; c < Q4; ++c) {
-          pq[tt][c] = phi<DT>(word_elem<DT>(qw[tt], c));
-          den[tt] = fma((double)pq[tt][c], zr[c], den[tt]);
-        }
+        for (int c = 0; c < Q4; ++c) pq[tt][c] = phi<DT>(word_elem<DT>(qw[tt], c));
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
+      for (int i = 0; i <= NT; ++i)
 #pragma unroll
         for (int s4 = 0; s4 < Q4 / 4; ++s4) {
           const u32x4 a = simg[(i * (Q4 / 4) + s4) * 64 + lane];
@@ -485,17 +485,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     }
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      const double rden = 1.0 / sum_groups(den[tt]);
-      const int64_t t = t0 + 16 * tt + n;
-      if (t < wg_end) {
+      // O = num / den: FP64 reciprocal, applied as its two-float expansion
+      // rh + rl (num * rh + num * rl with one rounding: within an ulp of
+      // the FP64 product rounded to fp32)
+      const double rden = 1.0 / (double)acc[tt][NT][0];
+      const float rh = (float)rden, rl = (float)(rden - (double)rh);
+      if (t0 + 16 * tt + n < wg_end) {
         uint32_t ow[OW];
 #pragma unroll
         for (int i = 0; i < NT; ++i)
 #pragma unroll
           for (int r = 0; r < 4; r += 2) {
-            // O = num / den: FP64 reciprocal of the FP64 normaliser, FP64 product
-            const float o0 = (float)((double)acc[tt][i][r] * rden);
-            const float o1 = (float)((double)acc[tt][i][r + 1] * rden);
+            const float o0 = fmaf(acc[tt][i][r], rh, acc[tt][i][r] * rl);
+            const float o1 = fmaf(acc[tt][i][r + 1], rh, acc[tt][i][r + 1] * rl);
             const int e = 4 * i + r;  // position in the lane's output run
             if constexpr (OT == DT_BF16) {
               ow[e >> 1] = pack_bf16(o0, o1);
@@ -504,15 +506,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
               ow[e + 1] = __float_as_uint(o1);
             }
           }
-        store_words<OB>(obase + t * osn * OES, ow);
+        store_words<OB>(oh + (t0 + 16 * tt) * orow_bytes + ooff, ow);
       }
     }
-    if (more) {
-#pragma unroll
-      for (int tt = 0; tt < TT; ++tt)
-#pragma unroll
-        for (int w = 0; w < QW; ++w) qcur[tt][w] = qnext[tt][w];
-    }
+  };
+
+  // two register sets in turn: the next step's queries are in flight in
+  // one while the other's step computes (no copies between them)
+  constexpr int STRIDE = 16 * TT * 4;
+  QRegs qa, qb;
+  int64_t t0 = wg_begin + 16 * TT * wave;
+  if (t0 < wg_end) load_q(t0, qa);
+  while (t0 < wg_end) {
+    const int64_t t1 = t0 + STRIDE;
+    if (t1 < wg_end) load_q(t1, qb);
+    compute(t0, qa);
+    if (t1 >= wg_end) break;
+    const int64_t t2 = t1 + STRIDE;
+    if (t2 < wg_end) load_q(t2, qa);
+    compute(t1, qb);
+    t0 = t2;
   }
 }
 
@@ -599,7 +612,7 @@ static hipError_t launch_apply_only(const FwdArgs& a) {
   ProfScope prof("apply", a.stream);
 #define LA_APPLY(DTI, DTO)                                                       \
   apply_kernel<DTI, DTO, D><<<agrid, 256, 0, a.stream>>>(                         \
-      a.q, a.sb, a.sh, a.sn, a.o, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img, a.z64)
+      a.q, a.sb, a.sh, a.sn, a.o, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img)
   if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) LA_APPLY(DT_BF16, DT_BF16);
   else if (a.in_dt == DT_BF16) LA_APPLY(DT_BF16, DT_FP32);
   else if (a.out_dt == DT_BF16) LA_APPLY(DT_FP32, DT_BF16);
@@ -619,7 +632,7 @@ hipError_t launch_forward(const FwdArgs& a) {
 }
 
 hipError_t launch_apply(const FwdArgs& a) {
-  hipError_t e = launch_images(a.S64, a.img, a.in_dt, a.B * a.H, a.D, a.stream);
+  hipError_t e = launch_images(a.S64, a.z64, a.img, a.in_dt, a.B * a.H, a.D, a.stream);
   if (e != hipSuccess) return e;
   switch (a.D) {
     case 16: return launch_apply_only<16>(a);
@@ -630,15 +643,15 @@ hipError_t launch_apply(const FwdArgs& a) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_images(const double* M64, void* img, int img_dt, int64_t BH, int D,
-                         hipStream_t stream) {
-  dim3 grid((D * D + 255) / 256, (unsigned)BH);
+hipError_t launch_images(const double* M64, const double* v64, void* img, int img_dt, int64_t BH,
+                         int D, hipStream_t stream) {
+  dim3 grid((D * D + D + 255) / 256, (unsigned)BH);
   ProfScope prof("images", stream);
   switch (D) {
-    case 16: image_kernel<16><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
-    case 32: image_kernel<32><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
-    case 64: image_kernel<64><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
-    case 128: image_kernel<128><<<grid, 256, 0, stream>>>(M64, img, img_dt); break;
+    case 16: image_kernel<16><<<grid, 256, 0, stream>>>(M64, v64, img, img_dt); break;
+    case 32: image_kernel<32><<<grid, 256, 0, stream>>>(M64, v64, img, img_dt); break;
+    case 64: image_kernel<64><<<grid, 256, 0, stream>>>(M64, v64, img, img_dt); break;
+    case 128: image_kernel<128><<<grid, 256, 0, stream>>>(M64, v64, img, img_dt); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -5,9 +5,11 @@
 
 namespace la {
 
-// Matrix-core operand images of a d x d matrix M (S or dS), per head.
-// Two images per head:
-//   T image: A[row = value feature e][k = key/query feature c] = M[c][e]
+// Matrix-core operand images of a d x d matrix M (S or dS), per head:
+//   T image: A[row = value feature e][k = key/query feature c] = M[c][e],
+//            followed by a z tile: A[row = any of 16][k = c] = v[c] (the
+//            normaliser z, or dz), whose product with phi(q) gives the
+//            normaliser of every token in every output row
 //   N image: A[row = key/query feature c][k = value feature e] = M[c][e]
 // A 16-row output tile i maps row m to feature (m/4)*Q4 + 4i + (m%4), so a
 // lane's four result rows over all tiles cover one contiguous run of Q4
@@ -21,18 +23,21 @@ struct ImageCfg {
   static constexpr int Q4 = D / 4;
   static constexpr int NT = D / 16;                  // output tiles
   static constexpr int NS = D >= 32 ? D / 32 : 1;    // bf16 k-steps of 32
-  static constexpr int BF16_BYTES = NT * NS * 2 * 64 * 16;  // one image
-  static constexpr int F32_BYTES = NT * (Q4 / 4) * 64 * 16;
-  static constexpr int img_bytes(int dt) { return dt == DT_BF16 ? BF16_BYTES : F32_BYTES; }
-  static constexpr int head_bytes(int dt) { return 2 * img_bytes(dt); }
+  static constexpr int TILE_BF16 = NS * 2 * 64 * 16;  // one 16-row tile, hi + lo
+  static constexpr int TILE_F32 = (Q4 / 4) * 64 * 16;
+  static constexpr int tile_bytes(int dt) { return dt == DT_BF16 ? TILE_BF16 : TILE_F32; }
+  // the NT matrix tiles of one image
+  static constexpr int mat_bytes(int dt) { return NT * tile_bytes(dt); }
+  // the T image: matrix tiles + z tile (the N image starts right after it)
+  static constexpr int img_bytes(int dt) { return (NT + 1) * tile_bytes(dt); }
+  static constexpr int head_bytes(int dt) { return img_bytes(dt) + mat_bytes(dt); }
 };
 
+// (word, slot) of element (tile i, row m, contraction index k).
 template <int D>
-__device__ __forceinline__ void image_slot(int row, int k, int& word, int& slot, int dt) {
+__device__ __forceinline__ void tile_slot(int i, int m, int k, int& word, int& slot, int dt) {
   using IC = ImageCfg<D>;
   constexpr int Q4 = IC::Q4;
-  const int gq = row / Q4, rrem = row % Q4;
-  const int i = rrem >> 2, m = 4 * gq + (rrem & 3);
   const int gk = k / Q4, krem = k % Q4;
   const int lane = 16 * gk + m;
   if (dt == DT_BF16) {
@@ -42,6 +47,32 @@ __device__ __forceinline__ void image_slot(int row, int k, int& word, int& slot,
   } else {
     slot = krem & 3;
     word = (i * (Q4 / 4) + (krem >> 2)) * 64 + lane;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void image_slot(int row, int k, int& word, int& slot, int dt) {
+  constexpr int Q4 = ImageCfg<D>::Q4;
+  const int gq = row / Q4, rrem = row % Q4;
+  tile_slot<D>(rrem >> 2, 4 * gq + (rrem & 3), k, word, slot, dt);
+}
+
+// Store val (FP64) at (word, slot) of an image: hi/lo bf16 parts or fp32.
+template <int D>
+__device__ __forceinline__ void put_image(char* base, int word, int slot, int dt, double val) {
+  if (dt == DT_BF16) {
+    const uint16_t hi = to_bf16((float)val);
+    const uint16_t lo = to_bf16((float)(val - (double)bf16f(hi)));
+    uint16_t* wh = (uint16_t*)(base + (int64_t)word * 16);
+    uint16_t* wl = (uint16_t*)(base + (int64_t)(word + 64) * 16);
+    wh[slot] = hi;
+    wl[slot] = lo;
+    if (ImageCfg<D>::Q4 < 8) {  // d = 16: slots 4..7 of each k-step are padding
+      wh[slot + 4] = 0;
+      wl[slot + 4] = 0;
+    }
+  } else {
+    ((float*)(base + (int64_t)word * 16))[slot] = (float)val;
   }
 }
 
@@ -55,21 +86,19 @@ __device__ __forceinline__ void write_images(void* img, int dt, int bh, int c, i
     const int k = which == 0 ? c : e;
     int word, slot;
     image_slot<D>(row, k, word, slot, dt);
-    char* base = head + which * IC::img_bytes(dt);
-    if (dt == DT_BF16) {
-      const uint16_t hi = to_bf16((float)val);
-      const uint16_t lo = to_bf16((float)(val - (double)bf16f(hi)));
-      uint16_t* wh = (uint16_t*)(base + (int64_t)word * 16);
-      uint16_t* wl = (uint16_t*)(base + (int64_t)(word + 64) * 16);
-      wh[slot] = hi;
-      wl[slot] = lo;
-      if (IC::Q4 < 8) {  // d = 16: slots 4..7 of each k-step are padding
-        wh[slot + 4] = 0;
-        wl[slot + 4] = 0;
-      }
-    } else {
-      ((float*)(base + (int64_t)word * 16))[slot] = (float)val;
-    }
+    put_image<D>(head + which * IC::img_bytes(dt), word, slot, dt, val);
+  }
+}
+
+// Store v[c] = val into all 16 rows of the T image's z tile of head bh.
+template <int D>
+__device__ __forceinline__ void write_z_tile(void* img, int dt, int bh, int c, double val) {
+  using IC = ImageCfg<D>;
+  char* head = (char*)img + (int64_t)bh * IC::head_bytes(dt);
+  for (int m = 0; m < 16; ++m) {
+    int word, slot;
+    tile_slot<D>(IC::NT, m, c, word, slot, dt);
+    put_image<D>(head, word, slot, dt, val);
   }
 }
 
@@ -117,7 +146,8 @@ hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v,
 hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
                           int img_dt, int64_t BH, int D, hipStream_t stream);
 hipError_t launch_backward(const BwdArgs& a);
-hipError_t launch_images(const double* M64, void* img, int img_dt, int64_t BH, int D,
-                         hipStream_t stream);
+// Images (both, with the z tile) of a given M and v.
+hipError_t launch_images(const double* M64, const double* v64, void* img, int img_dt, int64_t BH,
+                         int D, hipStream_t stream);
 
 }  // namespace la
