@@ -14,6 +14,8 @@
 // Passes: (1) images of S; (2) query kernel: dQ and per-token (1/den, dden);
 // (3) token reduction for dS, dz (the forward's summary kernel in its
 // backward mode); (4) FP64 combine of dS, dz; (5) key kernel: dK, dV.
+#include <type_traits>
+
 #include "la_kernels.h"
 #include "la_profile.h"
 
@@ -133,6 +135,41 @@ __device__ __forceinline__ void image_times_runs(
   }
 }
 
+// acc[t][0] += (one 16-row tile, e.g. the z tile) x B_t for the TT tiles of
+// a step; bf16 tiles hold hi then lo words per k-step.
+template <int DT, int D>
+__device__ __forceinline__ void tile_times_runs(
+    const u32x4* tile, int lane,
+    const uint32_t (&pw)[RowCfg<DT, D>::TT][RowCfg<DT, D>::PW],
+    f32x4 (&acc)[RowCfg<DT, D>::TT][1]) {
+  using C = RowCfg<DT, D>;
+  constexpr int TT = C::TT;
+  if constexpr (DT == DT_BF16) {
+#pragma unroll
+    for (int s = 0; s < C::NS; ++s) {
+      const bf16x8 hi = as_bf16x8(tile[(s * 2 + 0) * 64 + lane]);
+      const bf16x8 lo = as_bf16x8(tile[(s * 2 + 1) * 64 + lane]);
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const bf16x8 bt = as_bf16x8(u32x4{pw[t][4 * s], pw[t][4 * s + 1], pw[t][4 * s + 2], pw[t][4 * s + 3]});
+        acc[t][0] = mfma_bf16(hi, bt, acc[t][0]);
+        acc[t][0] = mfma_bf16(lo, bt, acc[t][0]);
+      }
+    }
+  } else {
+    constexpr int Q4 = C::Q4;
+#pragma unroll
+    for (int s4 = 0; s4 < Q4 / 4; ++s4) {
+      const u32x4 a = tile[s4 * 64 + lane];
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+          acc[t][0] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]), acc[t][0]);
+    }
+  }
+}
+
 template <int OT, int Q4>
 __device__ __forceinline__ void store_run(char* p, const float* x) {
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
@@ -166,7 +203,11 @@ __device__ __forceinline__ void stage_image(u32x4* dst, const u32x4* src, int wo
 
 // ---------------------------------------------------------------------------
 // Query kernel: dQ, plus (1/den, -(G . O)) per token for the dS/dz reduction.
-// LDS holds the N image of S (A[row = q feature c][k = value feature e]).
+// LDS holds the N image of S (A[row = q feature c][k = value feature e])
+// and the T image's z tile, whose product with phi(q) is den for every
+// output row.  bf16 inputs: the per-token dot product G . O and the dQ
+// combination run in fp32 (the terms come from bf16 data and fp32
+// matrix-core sums); fp32 inputs keep them in FP64.
 // ---------------------------------------------------------------------------
 template <int DT, int OT, int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_query_kernel(
@@ -176,70 +217,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     float2* __restrict__ stash) {
   using C = RowCfg<DT, D>;
   using IC = ImageCfg<D>;
+  using real = typename std::conditional<DT == DT_BF16, float, double>::type;
   constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int OB = Q4 * OES;
   constexpr int IMG_WORDS = IC::mat_bytes(DT) / 16;  // the N image
-  __shared__ u32x4 simg[IMG_WORDS];
+  constexpr int Z_WORDS = IC::tile_bytes(DT) / 16;   // the T image's z tile
+  __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
+  const u32x4* zimg = simg + IMG_WORDS;
 
   const int bh = blockIdx.y;
   const int64_t b = bh / H, h = bh % H;
-  stage_image(simg, (const u32x4*)((const char*)img + (int64_t)bh * IC::head_bytes(DT) +
-                                   IC::img_bytes(DT)),
-              IMG_WORDS, false);
+  {
+    const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT);
+    stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT)), IMG_WORDS, false);
+    stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT)), Z_WORDS, false);
+  }
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
-  double zr[Q4];
+  real zr[Q4];
 #pragma unroll
-  for (int c = 0; c < Q4; ++c) zr[c] = z64[(int64_t)bh * D + g * Q4 + c];
+  for (int c = 0; c < Q4; ++c) zr[c] = (real)z64[(int64_t)bh * D + g * Q4 + c];
   __syncthreads();
 
   const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
   const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
-  const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * C::RB;
-  const char* qbase = (const char*)q + in_head;
-  const char* gbase = (const char*)dout + in_head;
-  char* obase = (char*)dq + (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
+  // wave-uniform head pointers plus loop-invariant 32-bit lane offsets
+  const int64_t row_bytes = sn * C::ES, orow_bytes = osn * OES;
+  const char* qh = (const char*)q + (b * sb + h * sh) * C::ES;
+  const char* gh = (const char*)dout + (b * sb + h * sh) * C::ES;
+  char* oh = (char*)dq + (b * osb + h * osh) * OES;
+  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * C::RB);
+  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OB);
 
-  auto load_one = [&](int64_t t0, uint32_t* qw, uint32_t* gw) {
-    const int64_t t = t0 + n;
-    if (t < wg_end) {
-      load_words<C::RB>(qbase + t * sn * C::ES, qw);
-      load_words<C::RB>(gbase + t * sn * C::ES, gw);
+  // one tile's query and gradient runs
+  auto load_one = [&](int64_t tb, uint32_t* qw, uint32_t* gw) {
+    if (tb + n < wg_end) {
+      load_words<C::RB>(qh + tb * row_bytes + ioff, qw);
+      load_words<C::RB>(gh + tb * row_bytes + ioff, gw);
     } else {
 #pragma unroll
       for (int w = 0; w < C::RWD; ++w) { qw[w] = 0; gw[w] = 0; }
     }
   };
-  auto load = [&](int64_t t0, uint32_t (&qw)[C::PF ? TT : 1][C::RWD],
-                  uint32_t (&gw)[C::PF ? TT : 1][C::RWD]) {
+  constexpr int PT = C::PF ? TT : 1;  // tiles held ahead of their step
+  typedef uint32_t Regs[PT][2][C::RWD];
+  auto load = [&](int64_t t0, Regs& x) {
 #pragma unroll
-    for (int tt = 0; tt < (C::PF ? TT : 1); ++tt) load_one(t0 + 16 * tt, qw[tt], gw[tt]);
+    for (int tt = 0; tt < PT; ++tt) load_one(t0 + 16 * tt, x[tt][0], x[tt][1]);
   };
-  uint32_t qcur[C::PF ? TT : 1][C::RWD], gcur[C::PF ? TT : 1][C::RWD];
-  const int64_t first = wg_begin + 16 * TT * wave;
-  if constexpr (C::PF) {
-    if (first < wg_end) load(first, qcur, gcur);
-  }
-  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
-    // next step's inputs are in flight while this step computes
-    uint32_t qnext[C::PF ? TT : 1][C::RWD], gnext[C::PF ? TT : 1][C::RWD];
-    const bool more = C::PF && t0 + 16 * TT * 4 < wg_end;
+
+  auto compute = [&](int64_t t0, const Regs& x) {
     uint32_t pq[TT][C::PW], pg[TT][C::PW];
     if constexpr (C::PF) {
-      if (more) load(t0 + 16 * TT * 4, qnext, gnext);
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
-        phi_words<DT, D>(qcur[tt], pq[tt]);
-        raw_words<DT, D>(gcur[tt], pg[tt]);
+        phi_words<DT, D>(x[tt][0], pq[tt]);
+        raw_words<DT, D>(x[tt][1], pg[tt]);
       }
     } else {
       // load and convert one tile at a time (fewer live registers)
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
-        uint32_t one_q[1][C::RWD], one_g[1][C::RWD];
-        load_one(t0 + 16 * tt, one_q[0], one_g[0]);
-        phi_words<DT, D>(one_q[0], pq[tt]);
-        raw_words<DT, D>(one_g[0], pg[tt]);
+        uint32_t one[2][C::RWD];
+        load_one(t0 + 16 * tt, one[0], one[1]);
+        phi_words<DT, D>(one[0], pq[tt]);
+        raw_words<DT, D>(one[1], pg[tt]);
       }
     }
     f32x4 acc[TT][NT];
@@ -248,24 +291,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
       for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
     image_times_runs<DT, D, true>(simg, lane, pg, acc);  // X = S G
+    f32x4 dacc[TT][1];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) dacc[tt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+    tile_times_runs<DT, D>(zimg, lane, pq, dacc);        // den = phi(q) . z
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      double den = 0.0, gn = 0.0;
+      real gn = 0;
 #pragma unroll
       for (int i = 0; i < NT; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int c = 4 * i + r;
-          const double p = (double)run_val<DT>(pq[tt], c);
-          den = fma(p, zr[c], den);
-          gn = fma(p, (double)acc[tt][i][r], gn);
+          gn += (real)run_val<DT>(pq[tt], c) * (real)acc[tt][i][r];
         }
-      den = sum_groups(den);
       gn = sum_groups(gn);
-      const double rden = 1.0 / den;
-      const double go = gn * rden;  // G . O
-      const int64_t t = t0 + 16 * tt + n;
-      if (t < wg_end) {
+      const double rden = 1.0 / (double)dacc[tt][0][0];
+      const real go = (real)(gn * (real)rden);  // G . O
+      const real rd = (real)rden;
+      if (t0 + 16 * tt + n < wg_end) {
         float out[Q4];
 #pragma unroll
         for (int i = 0; i < NT; ++i)
@@ -273,18 +317,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
           for (int r = 0; r < 4; ++r) {
             const int c = 4 * i + r;
             const float dphi_c = fminf(run_val<DT>(pq[tt], c), 1.0f);
-            out[c] = (float)(fma(-go, zr[c], (double)acc[tt][i][r]) * rden) * dphi_c;
+            out[c] = (float)(fma(-go, zr[c], (real)acc[tt][i][r]) * rd) * dphi_c;
           }
-        store_run<OT, Q4>(obase + t * osn * OES, out);
-        if (g == 0) stash[(int64_t)bh * N + t] = float2{(float)rden, (float)(-go)};
+        store_run<OT, Q4>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
+        if (g == 0) stash[(int64_t)bh * N + t0 + 16 * tt + n] = float2{(float)rden, (float)(-go)};
       }
     }
-    if (more) {
-#pragma unroll
-      for (int tt = 0; tt < (C::PF ? TT : 1); ++tt)
-#pragma unroll
-        for (int w = 0; w < C::RWD; ++w) { qcur[tt][w] = qnext[tt][w]; gcur[tt][w] = gnext[tt][w]; }
-    }
+  };
+
+  // two register sets in turn where the registers allow a step ahead
+  constexpr int STRIDE = 16 * TT * 4;
+  Regs ra, rb;
+  int64_t t0 = wg_begin + 16 * TT * wave;
+  if (C::PF && t0 < wg_end) load(t0, ra);
+  while (t0 < wg_end) {
+    const int64_t t1 = t0 + STRIDE;
+    if (C::PF && t1 < wg_end) load(t1, rb);
+    compute(t0, ra);
+    if (t1 >= wg_end) break;
+    const int64_t t2 = t1 + STRIDE;
+    if (C::PF && t2 < wg_end) load(t2, ra);
+    compute(t1, rb);
+    t0 = t2;
   }
 }
 
