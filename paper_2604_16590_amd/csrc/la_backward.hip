@@ -22,8 +22,9 @@
 namespace la {
 
 // Layout shared by the query and key kernels: lane (g, n) holds token n of
-// a 16-token tile and the contiguous feature run [g*Q4, g*Q4 + Q4); the
-// matrix-core results of A x (that run) land in the same lane and run.
+// a 16-token tile and a run of Q4 = d/4 features (Run: 16-byte chunks
+// interleaved over the lane groups); the matrix-core results of A x (that
+// run) land in the same lane and run positions.
 template <int DT, int D>
 struct RowCfg {
   static constexpr int Q4 = D / 4;
@@ -170,24 +171,6 @@ __device__ __forceinline__ void tile_times_runs(
   }
 }
 
-template <int OT, int Q4>
-__device__ __forceinline__ void store_run(char* p, const float* x) {
-  constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int OB = Q4 * OES;
-  constexpr int OW = OB >= 4 ? OB / 4 : 1;
-  uint32_t ow[OW];
-#pragma unroll
-  for (int c = 0; c < Q4; c += 2) {
-    if constexpr (OT == DT_BF16) {
-      ow[c >> 1] = pack_bf16(x[c], x[c + 1]);
-    } else {
-      ow[c] = __float_as_uint(x[c]);
-      ow[c + 1] = __float_as_uint(x[c + 1]);
-    }
-  }
-  store_words<OB>(p, ow);
-}
-
 // Copy `words` 16-byte words of an image into LDS; with `hi_only` only the
 // hi half of each (tile, k-step) pair of a bf16 image is kept.
 __device__ __forceinline__ void stage_image(u32x4* dst, const u32x4* src, int words, bool hi_only) {
@@ -220,7 +203,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   using real = typename std::conditional<DT == DT_BF16, float, double>::type;
   constexpr int Q4 = C::Q4, NT = C::NT, TT = C::TT;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int OB = Q4 * OES;
   constexpr int IMG_WORDS = IC::mat_bytes(DT) / 16;  // the N image
   constexpr int Z_WORDS = IC::tile_bytes(DT) / 16;   // the T image's z tile
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
@@ -237,7 +219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const int g = lane >> 4, n = lane & 15;
   real zr[Q4];
 #pragma unroll
-  for (int c = 0; c < Q4; ++c) zr[c] = (real)z64[(int64_t)bh * D + g * Q4 + c];
+  for (int c = 0; c < Q4; ++c) zr[c] = (real)z64[(int64_t)bh * D + Run<D, DT>::feature(g, c)];
   __syncthreads();
 
   const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
@@ -247,14 +229,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const char* qh = (const char*)q + (b * sb + h * sh) * C::ES;
   const char* gh = (const char*)dout + (b * sb + h * sh) * C::ES;
   char* oh = (char*)dq + (b * osb + h * osh) * OES;
-  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * C::RB);
-  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OB);
+  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * Run<D, DT>::CB);
+  const uint32_t ooff =
+      (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * Run<D, DT>::CH * OES);
 
   // one tile's query and gradient runs
   auto load_one = [&](int64_t tb, uint32_t* qw, uint32_t* gw) {
     if (tb + n < wg_end) {
-      load_words<C::RB>(qh + tb * row_bytes + ioff, qw);
-      load_words<C::RB>(gh + tb * row_bytes + ioff, gw);
+      load_run<D, DT>(qh + tb * row_bytes + ioff, qw);
+      load_run<D, DT>(gh + tb * row_bytes + ioff, gw);
     } else {
 #pragma unroll
       for (int w = 0; w < C::RWD; ++w) { qw[w] = 0; gw[w] = 0; }
@@ -319,7 +302,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
             const float dphi_c = fminf(run_val<DT>(pq[tt], c), 1.0f);
             out[c] = (float)(fma(-go, zr[c], (real)acc[tt][i][r]) * rd) * dphi_c;
           }
-        store_run<OT, Q4>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
+        store_run<D, DT, OT>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
         if (g == 0) stash[(int64_t)bh * N + t0 + 16 * tt + n] = float2{(float)rden, (float)(-go)};
       }
     }
@@ -374,22 +357,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   double dzr[DO_K ? Q4 : 1];
   if constexpr (DO_K) {
 #pragma unroll
-    for (int c = 0; c < Q4; ++c) dzr[c] = dz64[(int64_t)bh * D + g * Q4 + c];
+    for (int c = 0; c < Q4; ++c) dzr[c] = dz64[(int64_t)bh * D + Run<D, DT>::feature(g, c)];
   }
   __syncthreads();
 
   const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
   const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
-  const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * C::RB;
+  const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * Run<D, DT>::CB;
   const char* kbase = (const char*)k + in_head;
   const char* vbase = (const char*)v + in_head;
-  const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Q4 * OES;
+  const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Run<D, DT>::CH * OES;
 
   auto load_one = [&](int64_t t0, uint32_t* kw, uint32_t* vw) {
     const int64_t t = t0 + n;
     if (t < wg_end) {
-      load_words<C::RB>(kbase + t * sn * C::ES, kw);
-      if (DO_K) load_words<C::RB>(vbase + t * sn * C::ES, vw);
+      load_run<D, DT>(kbase + t * sn * C::ES, kw);
+      if (DO_K) load_run<D, DT>(vbase + t * sn * C::ES, vw);
     } else {
 #pragma unroll
       for (int w = 0; w < C::RWD; ++w) { kw[w] = 0; vw[w] = 0; }
@@ -443,7 +426,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
           for (int i = 0; i < NT; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) out[4 * i + r] = acc[tt][i][r];
-          store_run<OT, Q4>((char*)dv + out_head + t * osn * OES, out);
+          store_run<D, DT, OT>((char*)dv + out_head + t * osn * OES, out);
         }
       }
     }
@@ -467,7 +450,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
               const float dphi_c = fminf(run_val<DT>(pk[tt], c), 1.0f);
               out[c] = (float)((double)acc[tt][i][r] + dzr[c]) * dphi_c;
             }
-          store_run<OT, Q4>((char*)dk + out_head + t * osn * OES, out);
+          store_run<D, DT, OT>((char*)dk + out_head + t * osn * OES, out);
         }
       }
     }

@@ -347,9 +347,9 @@ __global__ __launch_bounds__(256) void image_kernel(const double* __restrict__ M
 
 // ---------------------------------------------------------------------------
 // Apply: O^T = S^T phi(Q)^T per 16-token tile.  Lane (g, n) holds token n
-// and query features [g*Q4, g*Q4 + Q4) (Q4 = d/4), read as one contiguous
-// run; the matrix-core result puts value features [g*Q4, g*Q4 + Q4) of the
-// same token in the same lane.  The normaliser den = phi(q) . z comes from
+// and a run of Q4 = d/4 query features (Run: 16-byte chunks interleaved
+// over the lane groups); the matrix-core result puts the value features of
+// the same run positions of the same token in the same lane.  The normaliser den = phi(q) . z comes from
 // the same matrix-core pass (the image's z tile: every output row of it is
 // den of the lane's token), so the FP64 division and the store stay
 // in-lane.  The S^T operands (bf16 hi + lo parts, or fp32) sit in LDS for
@@ -362,7 +362,7 @@ struct ApplyCfg {
   static constexpr int TT = DT == DT_FP32 && D >= 128 ? 1 : 2;
   static constexpr int ES = DT == DT_BF16 ? 2 : 4;
   static constexpr int QB = D / 4 * ES;             // bytes of a lane's query run
-  static constexpr int QW = QB >= 4 ? QB / 4 : 1;
+  static constexpr int QW = QB / 4;
 };
 
 template <int DT, int OT, int D>
@@ -376,9 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   constexpr int NT = D / 16;
   constexpr int ES = AC::ES;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
-  constexpr int QB = AC::QB, QW = AC::QW;
-  constexpr int OB = Q4 * OES;
-  constexpr int OW = OB >= 4 ? OB / 4 : 1;
+  constexpr int QW = AC::QW;
   constexpr int IMG_WORDS = IC::img_bytes(DT) / 16;
   constexpr int TT = AC::TT;
   __shared__ u32x4 simg[IMG_WORDS];
@@ -401,19 +399,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const int64_t row_bytes = sn * ES, orow_bytes = osn * OES;
   const char* qh = (const char*)q + (b * sb + h * sh) * ES;
   char* oh = (char*)o + (b * osb + h * osh) * OES;
-  const uint32_t qoff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * QB);
-  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OB);
+  using RN = Run<D, DT>;
+  const uint32_t qoff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
+  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * RN::CH * OES);
 
   typedef uint32_t QRegs[TT][QW];
   auto load_q = [&](int64_t t0, QRegs& qw) {
     if (t0 + 16 * TT <= wg_end) {
 #pragma unroll
-      for (int tt = 0; tt < TT; ++tt) load_words<QB>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+      for (int tt = 0; tt < TT; ++tt) load_run<D, DT>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
     } else {
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
         if (t0 + 16 * tt + n < wg_end) {
-          load_words<QB>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+          load_run<D, DT>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
         } else {
 #pragma unroll
           for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
@@ -491,22 +490,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
       const double rden = 1.0 / (double)acc[tt][NT][0];
       const float rh = (float)rden, rl = (float)(rden - (double)rh);
       if (t0 + 16 * tt + n < wg_end) {
-        uint32_t ow[OW];
+        float out[Q4];
 #pragma unroll
         for (int i = 0; i < NT; ++i)
 #pragma unroll
-          for (int r = 0; r < 4; r += 2) {
-            const float o0 = fmaf(acc[tt][i][r], rh, acc[tt][i][r] * rl);
-            const float o1 = fmaf(acc[tt][i][r + 1], rh, acc[tt][i][r + 1] * rl);
-            const int e = 4 * i + r;  // position in the lane's output run
-            if constexpr (OT == DT_BF16) {
-              ow[e >> 1] = pack_bf16(o0, o1);
-            } else {
-              ow[e] = __float_as_uint(o0);
-              ow[e + 1] = __float_as_uint(o1);
-            }
-          }
-        store_words<OB>(oh + (t0 + 16 * tt) * orow_bytes + ooff, ow);
+          for (int r = 0; r < 4; ++r)
+            out[4 * i + r] = fmaf(acc[tt][i][r], rh, acc[tt][i][r] * rl);
+        store_run<D, DT, OT>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
       }
     }
   };

@@ -5,19 +5,73 @@
 
 namespace la {
 
+// Lane runs of the row kernels (apply, query and key backward).  Lane
+// (g, n) holds Q4 = d/4 features of token n: chunk w (CH features, 16 bytes
+// of the input type) of lane group g is features [4*CH*w + CH*g, +CH), so
+// one load or store instruction of the wave covers 4*CH contiguous features
+// of each of its 16 tokens.  Run position c = CH*w + j <-> feature
+// 4*CH*w + CH*g + j.
+template <int D, int DT>
+struct Run {
+  static constexpr int ES = DT == DT_BF16 ? 2 : 4;
+  static constexpr int Q4 = D / 4;
+  static constexpr int CH = 16 / ES < Q4 ? 16 / ES : Q4;  // features per chunk
+  static constexpr int NCH = Q4 / CH;                      // chunks per run
+  static constexpr int CB = CH * ES;                       // bytes per chunk
+  static __host__ __device__ constexpr int feature(int g, int c) {
+    return (c / CH) * 4 * CH + g * CH + c % CH;
+  }
+  static __host__ __device__ constexpr int group(int f) { return (f % (4 * CH)) / CH; }
+  static __host__ __device__ constexpr int pos(int f) { return (f / (4 * CH)) * CH + f % CH; }
+};
+
+// Load a lane's run (p = row start + CB * g) into words, chunk by chunk.
+template <int D, int DT>
+__device__ __forceinline__ void load_run(const char* p, uint32_t* w) {
+  using R = Run<D, DT>;
+  constexpr int CW = R::CB / 4;
+#pragma unroll
+  for (int c = 0; c < R::NCH; ++c) load_words<R::CB>(p + c * 4 * R::CB, w + c * CW);
+}
+
+// Store a lane's run of output values x[0..Q4) as type OT (p = row start +
+// CH * sizeof(OT) * g), chunk by chunk; bf16 rounds to nearest even.
+template <int D, int DT, int OT>
+__device__ __forceinline__ void store_run(char* p, const float* x) {
+  using R = Run<D, DT>;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int OCB = R::CH * OES;  // output bytes per chunk
+  constexpr int OW = OCB / 4;
+#pragma unroll
+  for (int c = 0; c < R::NCH; ++c) {
+    uint32_t ow[OW];
+#pragma unroll
+    for (int j = 0; j < R::CH; j += 2) {
+      const float a = x[c * R::CH + j], b = x[c * R::CH + j + 1];
+      if constexpr (OT == DT_BF16) {
+        ow[j >> 1] = pack_bf16(a, b);
+      } else {
+        ow[j] = __float_as_uint(a);
+        ow[j + 1] = __float_as_uint(b);
+      }
+    }
+    store_words<OCB>(p + c * 4 * OCB, ow);
+  }
+}
+
 // Matrix-core operand images of a d x d matrix M (S or dS), per head:
 //   T image: A[row = value feature e][k = key/query feature c] = M[c][e],
 //            followed by a z tile: A[row = any of 16][k = c] = v[c] (the
 //            normaliser z, or dz), whose product with phi(q) gives the
 //            normaliser of every token in every output row
 //   N image: A[row = key/query feature c][k = value feature e] = M[c][e]
-// A 16-row output tile i maps row m to feature (m/4)*Q4 + 4i + (m%4), so a
-// lane's four result rows over all tiles cover one contiguous run of Q4
-// features.  The contraction index k maps to lane group g' = k / Q4 and
-// position k % Q4 inside that group's run, matching how the B operand
-// (one token per lane, a contiguous feature run per lane group) is loaded.
-// bf16 images store a hi part bf16(M) and a lo part bf16(M - hi); fp32
-// images store float(M).
+// A 16-row output tile i maps row m = 4g + r to the feature at run
+// position 4i + r of lane group g (Run above), so a lane's four result rows
+// over all tiles are its run of output features.  The contraction index k
+// maps to lane group Run::group(k) and run position Run::pos(k), matching
+// how the B operand (one token per lane, a feature run per lane group) is
+// loaded.  bf16 images store a hi part bf16(M) and a lo part bf16(M - hi);
+// fp32 images store float(M).
 template <int D>
 struct ImageCfg {
   static constexpr int Q4 = D / 4;
@@ -38,13 +92,17 @@ template <int D>
 __device__ __forceinline__ void tile_slot(int i, int m, int k, int& word, int& slot, int dt) {
   using IC = ImageCfg<D>;
   constexpr int Q4 = IC::Q4;
-  const int gk = k / Q4, krem = k % Q4;
-  const int lane = 16 * gk + m;
   if (dt == DT_BF16) {
+    using R = Run<D, DT_BF16>;
+    const int krem = R::pos(k);
+    const int lane = 16 * R::group(k) + m;
     const int s = krem >> 3;
     slot = krem & 7;
     word = ((i * IC::NS + s) * 2) * 64 + lane;  // hi part; lo part is +64
   } else {
+    using R = Run<D, DT_FP32>;
+    const int krem = R::pos(k);
+    const int lane = 16 * R::group(k) + m;
     slot = krem & 3;
     word = (i * (Q4 / 4) + (krem >> 2)) * 64 + lane;
   }
@@ -52,8 +110,14 @@ __device__ __forceinline__ void tile_slot(int i, int m, int k, int& word, int& s
 
 template <int D>
 __device__ __forceinline__ void image_slot(int row, int k, int& word, int& slot, int dt) {
-  constexpr int Q4 = ImageCfg<D>::Q4;
-  const int gq = row / Q4, rrem = row % Q4;
+  int gq, rrem;
+  if (dt == DT_BF16) {
+    gq = Run<D, DT_BF16>::group(row);
+    rrem = Run<D, DT_BF16>::pos(row);
+  } else {
+    gq = Run<D, DT_FP32>::group(row);
+    rrem = Run<D, DT_FP32>::pos(row);
+  }
   tile_slot<D>(rrem >> 2, 4 * gq + (rrem & 3), k, word, slot, dt);
 }
 
