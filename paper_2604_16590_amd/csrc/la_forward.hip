@@ -63,9 +63,22 @@ struct SummaryRegs {
   float2 tok;
 };
 
-// The pair of token R*g + r of this lane's group (lane 16g + r holds it).
+// The pair of token R*g + r of this lane's group (lane 16g + r holds it):
+// a DPP row broadcast (rows of the DPP unit are the 16-lane groups), a
+// plain VALU move with no LDS round trip.  r is a constant after
+// unrolling, so the switch folds to one case.
+template <int L>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + L,
+                                                               0xf, 0xf, false));
+}
 __device__ __forceinline__ float2 group_bcast(float2 v, int r) {
-  return float2{__shfl(v.x, r, 16), __shfl(v.y, r, 16)};
+  switch (r) {
+#define LA_BC(L) case L: return float2{row_bcast<L>(v.x), row_bcast<L>(v.y)};
+    LA_BC(0) LA_BC(1) LA_BC(2) LA_BC(3) LA_BC(4) LA_BC(5) LA_BC(6) LA_BC(7)
+#undef LA_BC
+    default: return float2{0.f, 0.f};
+  }
 }
 
 // Rows past the end of the range load K = -inf (phi = 0) and V = 0, so
