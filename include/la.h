@@ -245,6 +245,8 @@ typedef struct {
   void* o;                /* output (server-owned for generated requests) */
   double* s;              /* [B][H][d][d] FP64 summary, server-owned */
   double* z;              /* [B][H][d]    FP64 normaliser, server-owned */
+  double gen_ms;          /* device time generating inputs, summed over slices */
+  double attn_ms;         /* device time of the attention, summed over slices */
 } la_result;
 
 typedef struct {

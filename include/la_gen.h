@@ -9,11 +9,14 @@
  *
  *  - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).  Element e of the
  *    logical [b_offset + B, H, N, d] tensor (row-major flat index; the
- *    filled tensor is its batches b_offset .. b_offset + B - 1) uses counter
- *    (lo32(e>>1), hi32(e>>1), stream, 0) and key (lo32(seed), hi32(seed)).
- *  - u1 = ((x0 >> 9) + 0.5) * 2^-23, u2 = (x1 >> 8) * 2^-24 (exact in
- *    FP32); Box-Muller in FP32: r = sqrt(-2 ln u1), t = 2 pi u2; even e takes
- *    r cos t, odd e takes r sin t.
+ *    filled tensor is its batches b_offset .. b_offset + B - 1) is in pair
+ *    p = e >> 1, which uses Philox block c = p >> 1: counter
+ *    (lo32(c), hi32(c), stream, 0), key (lo32(seed), hi32(seed)), and of the
+ *    block's output words (w0, w1) = (x0, x1) for even p, (x2, x3) for odd p.
+ *  - u1 = ((w0 >> 9) + 0.5) * 2^-23, u2 = (w1 >> 8) * 2^-24 (exact in
+ *    FP32); Box-Muller in FP32: r = sqrt(-2 ln u1); with t = 2 pi u2 even e
+ *    takes r cos t, odd e takes r sin t, cos t and sin t rounded to FP32
+ *    (evaluated as cospi/sinpi of 2 u2, exact in FP32).
  *  - value = mean + std * normal (+ grid structure when grid_T > 0):
  *    token n = (t*n_lat + i)*n_lon + j; channel c of tensor `tensor_id`
  *    and head h adds amplitude * sin(m_c lon_j + l_c lat_i + 2 pi t/T + psi)

@@ -19,8 +19,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += W0; k1 += W1; }
-    const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
-    const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+    // one 32 x 32 -> 64-bit product each (both halves from one instruction)
+    const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c[1] ^ k0, n1 = lo1, n2 = hi0 ^ c[3] ^ k1, n3 = lo0;
     c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
   }
@@ -59,8 +61,41 @@ __device__ __forceinline__ float structure(const GenArgs& a, int h, uint32_t n, 
   return a.amplitude * sinf(m * lon + l * lat + 2.0f * kPi * (float)t / (float)a.grid_T + psi);
 }
 
+// Box-Muller of one pair of uniform words (FP32, every step rounded on its
+// own: the file is built without contraction, like its host mirror).
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float& z0, float& z1) {
+  const float u1 = ((float)(w0 >> 9) + 0.5f) * 0x1p-23f;
+  const float t = (float)(w1 >> 8) * 0x1p-23f;  // 2 u2, exact
+  const float r = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(t, &s, &c);  // sin, cos of pi t = 2 pi u2 (no range reduction)
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// Store elements (e0, e0 + 1) of a head at token n, channel cc.
+__device__ __forceinline__ void store_pair(const GenArgs& a, char* head, int h, uint32_t n,
+                                           uint32_t cc, float z0, float z1) {
+  float f[2] = {z0, z1};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float val = a.mean + a.std * f[s];
+    if (a.grid_T > 0) val += structure(a, h, n, cc + s);
+    f[s] = val;
+  }
+  const int64_t off = (int64_t)n * a.sn + cc;
+  if (a.dtype == 0) {
+    const uint32_t w = (uint32_t)f32_to_bf16_rne(f[0]) | ((uint32_t)f32_to_bf16_rne(f[1]) << 16);
+    *(uint32_t*)((uint16_t*)head + off) = w;
+  } else {
+    *(float2*)((float*)head + off) = float2{f[0], f[1]};
+  }
+}
+
 // Grid: y = (b, h) of the filled tensor, x strides over the head's element
-// pairs (a pair shares one Philox call and one Box-Muller transform).
+// pairs.  Pair p of the logical tensor takes Philox block p >> 1 and its
+// words (x0, x1) for even p, (x2, x3) for odd p; with d % 4 == 0 a thread
+// makes both pairs of a block from one Philox call.
 __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
   const int64_t bh = blockIdx.y;
   const int64_t b = bh / a.H, h = bh % a.H;
@@ -68,32 +103,34 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
   const int64_t head_pairs = a.N * a.d / 2;
   const int64_t base = ((a.b_offset + b) * a.H + h) * head_pairs;  // logical pair index
   char* head = (char*)a.dst + (b * a.sb + h * a.sh) * (a.dtype == 0 ? 2 : 4);
-  const float kTwoPi = 6.28318530717959f;
-  for (int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pl < head_pairs;
-       pl += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t lp = (uint64_t)(base + pl);
-    uint32_t c[4] = {(uint32_t)lp, (uint32_t)(lp >> 32), a.stream, 0u};
-    philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-    const float u1 = ((float)(c[0] >> 9) + 0.5f) * 0x1p-23f;
-    const float u2 = (float)(c[1] >> 8) * 0x1p-24f;
-    const float r = sqrtf(-2.0f * logf(u1));
-    const float t = kTwoPi * u2;
-    const float z[2] = {r * cosf(t), r * sinf(t)};
-    const uint32_t e0 = (uint32_t)(2 * pl);  // element within the head (N * d < 2^32)
-    const uint32_t n = e0 / d, cc = e0 - n * d;
-    float f[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      float val = a.mean + a.std * z[s];
-      if (a.grid_T > 0) val += structure(a, (int)h, n, cc + s);
-      f[s] = val;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if ((d & 3) == 0) {
+    // base is even here (head_pairs is even), so blocks never straddle heads
+    const int64_t head_quads = head_pairs / 2;
+    for (int64_t ql = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ql < head_quads; ql += stride) {
+      const uint64_t blk = (uint64_t)(base / 2 + ql);
+      uint32_t c[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), a.stream, 0u};
+      philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      float z0, z1, z2, z3;
+      box_muller(c[0], c[1], z0, z1);
+      box_muller(c[2], c[3], z2, z3);
+      const uint32_t e0 = (uint32_t)(4 * ql);  // element within the head (N * d < 2^32)
+      const uint32_t n = e0 / d, cc = e0 - n * d;
+      store_pair(a, head, (int)h, n, cc, z0, z1);
+      store_pair(a, head, (int)h, n, cc + 2, z2, z3);
     }
-    const int64_t off = (int64_t)n * a.sn + cc;
-    if (a.dtype == 0) {
-      const uint32_t w = (uint32_t)f32_to_bf16_rne(f[0]) | ((uint32_t)f32_to_bf16_rne(f[1]) << 16);
-      *(uint32_t*)((uint16_t*)head + off) = w;
-    } else {
-      *(float2*)((float*)head + off) = float2{f[0], f[1]};
+  } else {
+    for (int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pl < head_pairs; pl += stride) {
+      const uint64_t lp = (uint64_t)(base + pl);
+      const uint64_t blk = lp >> 1;
+      uint32_t c[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), a.stream, 0u};
+      philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      float z0, z1;
+      if (lp & 1) box_muller(c[2], c[3], z0, z1);
+      else box_muller(c[0], c[1], z0, z1);
+      const uint32_t e0 = (uint32_t)(2 * pl);
+      const uint32_t n = e0 / d, cc = e0 - n * d;
+      store_pair(a, head, (int)h, n, cc, z0, z1);
     }
   }
 }

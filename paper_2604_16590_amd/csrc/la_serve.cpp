@@ -98,7 +98,7 @@ struct Slice {
   int64_t b0, m;       // members [b0, b0 + m)
   size_t off, bytes;   // transient block: generated inputs + workspace
   int stream;
-  hipEvent_t done;
+  hipEvent_t start, gen, done;  // timed events: slice start, inputs ready, done
   uint64_t t_fake_done;
   bool fail;
 };
@@ -112,6 +112,7 @@ struct Request {
   int slices_started = 0, slices_done = 0;
   bool failed = false;
   size_t keep_off = 0, keep_bytes = 0;  // S, z (+ O when generated)
+  double gen_ms = 0.0, attn_ms = 0.0;    // device time summed over slices
   bool keep_held = false;
   void* o = nullptr;
   double* s = nullptr;
@@ -179,7 +180,7 @@ hipEvent_t take_event(la_server* s) {
   }
   hipEvent_t e = nullptr;
   if (s->cfg.fake_executor) return e;
-  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -197,6 +198,7 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
   char* blk = s->base + sl.off;
   const void *q, *k, *v;
   void* o;
+  if (hipEventRecord(sl.start, st) != hipSuccess) return LA_ERR_HIP;
   if (r.generate) {
     d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh; d.in_sn = d.d;
     d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh; d.out_sn = d.d;
@@ -227,6 +229,7 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
     v = (const char*)r.v + sl.b0 * d.in_sb * ie;
     o = (char*)r.o + sl.b0 * d.out_sb * oe;
   }
+  if (hipEventRecord(sl.gen, st) != hipSuccess) return LA_ERR_HIP;
   size_t ws = 0;
   la_workspace_size(&d, 0, &ws);
   double* S = rq.s + (size_t)sl.b0 * d.H * d.d * d.d;
@@ -239,8 +242,17 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
 
 void finish_slice(la_server* s, Slice& sl, bool ok) {
   s->arena.release(sl.off, sl.bytes);
-  if (sl.done) s->events.push_back(sl.done);
   auto it = s->reqs.find(sl.req);
+  if (ok && it != s->reqs.end() && sl.start && sl.gen && sl.done) {
+    float g = 0.f, a = 0.f;
+    if (hipEventElapsedTime(&g, sl.start, sl.gen) == hipSuccess &&
+        hipEventElapsedTime(&a, sl.gen, sl.done) == hipSuccess) {
+      it->second.gen_ms += g;
+      it->second.attn_ms += a;
+    }
+  }
+  for (hipEvent_t e : {sl.start, sl.gen, sl.done})
+    if (e) s->events.push_back(e);
   if (it == s->reqs.end()) return;
   Request& rq = it->second;
   rq.slices_done += 1;
@@ -325,9 +337,16 @@ int admit(la_server* s) {
     if (!s->arena.alloc(sl.bytes, &sl.off)) break;
     sl.stream = s->next_stream;
     s->next_stream = (s->next_stream + 1) % std::max(1, (int)s->streams.size());
+    sl.start = take_event(s);
+    sl.gen = take_event(s);
     sl.done = take_event(s);
     sl.fail = s->fail_at.count({id, sl.index}) > 0;
-    if (!s->cfg.fake_executor && !sl.done) { s->arena.release(sl.off, sl.bytes); break; }
+    if (!s->cfg.fake_executor && !(sl.start && sl.gen && sl.done)) {
+      for (hipEvent_t e : {sl.start, sl.gen, sl.done})
+        if (e) s->events.push_back(e);
+      s->arena.release(sl.off, sl.bytes);
+      break;
+    }
     if (rq.state == LA_REQ_QUEUED) {
       rq.state = LA_REQ_RUNNING;
       rq.t_admit = now_ns();
@@ -482,6 +501,8 @@ la_status la_serve_poll(la_server* s, uint64_t id, la_result* out) {
   r.o = rq.o;
   r.s = rq.s;
   r.z = rq.z;
+  r.gen_ms = rq.gen_ms;
+  r.attn_ms = rq.attn_ms;
   *out = r;
   return LA_OK;
 }

@@ -10,11 +10,14 @@ library ``liblagen.so``); both follow one definition:
   0xBB67AE85.
 * Element e of the logical [b_offset + B, H, N, d] tensor (row-major flat
   index; a generated tensor holds batches b_offset .. b_offset + B - 1) takes
-  pair index p = e >> 1, counter (lo32 p, hi32 p, stream, 0) and key
-  (lo32 seed, hi32 seed).  From the first two output words
-  u1 = ((x0 >> 9) + 0.5) * 2^-23 and u2 = (x1 >> 8) * 2^-24; Box-Muller in
-  FP32 gives r = sqrt(-2 ln u1), t = 2 pi u2, and the element takes
-  r cos t (even e) or r sin t (odd e).
+  pair index p = e >> 1 and Philox block c = p >> 1: counter
+  (lo32 c, hi32 c, stream, 0), key (lo32 seed, hi32 seed).  The pair uses
+  output words (w0, w1) = (x0, x1) for even p and (x2, x3) for odd p:
+  u1 = ((w0 >> 9) + 0.5) * 2^-23, u2 = (w1 >> 8) * 2^-24; Box-Muller in FP32
+  gives r = sqrt(-2 ln u1), and with t = 2 pi u2 the element takes
+  r cos t (even e) or r sin t (odd e), where cos t and sin t are the FP32
+  roundings of the exact values (the device evaluates them as sinpi/cospi
+  of 2 u2, which is exact in FP32).
 * value = mean + std * normal (+ the optional grid structure below), all in
   FP32, then (for bfloat16) float32 -> bfloat16 round to nearest even.
 * Grid structure (spatiotemporal token grids of T frames x lat x lon
@@ -77,16 +80,20 @@ def normal_values(spec: GenSpec, flat_index: np.ndarray) -> np.ndarray:
     """FP64 N(0,1) draws for the given flat element indices."""
     e = np.asarray(flat_index, np.uint64)
     p = e >> np.uint64(1)
-    x0, x1, _, _ = philox4x32_10(p & np.uint64(MASK), p >> np.uint64(32),
-                                 np.full_like(p, spec.stream), np.zeros_like(p),
-                                 spec.seed & MASK, (spec.seed >> 32) & MASK)
+    c = p >> np.uint64(1)
+    y0, y1, y2, y3 = philox4x32_10(c & np.uint64(MASK), c >> np.uint64(32),
+                                   np.full_like(c, spec.stream), np.zeros_like(c),
+                                   spec.seed & MASK, (spec.seed >> 32) & MASK)
+    odd_pair = (p & np.uint64(1)).astype(bool)
+    x0 = np.where(odd_pair, y2, y0)
+    x1 = np.where(odd_pair, y3, y1)
     f32 = np.float32
     u1 = ((x0 >> np.uint64(9)).astype(f32) + f32(0.5)) * f32(2.0 ** -23)
     u2 = (x1 >> np.uint64(8)).astype(f32) * f32(2.0 ** -24)
     r = np.sqrt(f32(-2.0) * np.log(u1))
-    t = f32(6.28318530717959) * u2
+    t = (f32(2.0) * u2).astype(np.float64) * np.pi  # 2 pi u2, rounded once below
     odd = (e & np.uint64(1)).astype(bool)
-    return np.where(odd, r * np.sin(t), r * np.cos(t)).astype(f32)
+    return np.where(odd, r * np.sin(t).astype(f32), r * np.cos(t).astype(f32)).astype(f32)
 
 
 def structure_values(spec: GenSpec, B, H, N, d, flat_index) -> np.ndarray:

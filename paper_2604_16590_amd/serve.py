@@ -32,7 +32,8 @@ class Result(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32),
                 ("t_arrival_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_done_ns", ctypes.c_uint64), ("slices", ctypes.c_int32),
-                ("o", ctypes.c_void_p), ("s", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+                ("o", ctypes.c_void_p), ("s", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("gen_ms", ctypes.c_double), ("attn_ms", ctypes.c_double)]
 
 
 class Counters(ctypes.Structure):
@@ -166,15 +167,23 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
         for rid in list(pending):
             r = server.poll(rid)
             if r.state in (DONE, FAILED):
-                done.append((rid, pending.pop(rid), r.state, r.t_arrival_ns, r.t_admit_ns, r.t_done_ns))
+                done.append((rid, pending.pop(rid), r.state, r.t_arrival_ns, r.t_admit_ns, r.t_done_ns,
+                             r.gen_ms, r.attn_ms))
                 server.release(rid)
         if i < n_requests:
             time.sleep(max(0.0, min(1e-4, (arrivals[i] - time.monotonic_ns()) / 1e9)))
         else:
             time.sleep(1e-4)
-    lat = [(t_done - t_arr) / 1e6 for _, _, st, t_arr, _, t_done in done if st == DONE]
+    ok = [x for x in done if x[2] == DONE]
+    lat = [(x[5] - x[3]) / 1e6 for x in ok]
     span = (max(x[5] for x in done) - min(x[3] for x in done)) / 1e9
     tokens = sum(n * members for _, n, st, *_ in done if st == DONE)
+    # device time per request, split into input generation (standing in for
+    # the upstream projection) and attention; slices of different requests
+    # overlap on the device, so these are per-stream times, not shares of
+    # the wall clock
+    gen_ms = sum(x[6] for x in ok)
+    attn_ms = sum(x[7] for x in ok)
     return {"requests": n_requests, "completed": len(lat),
             "failed": sum(1 for x in done if x[2] == FAILED),
             "offered_req_per_s": rate_per_s,
@@ -182,7 +191,9 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
             "max_ms": max(lat) if lat else None,
             "tokens_per_s": tokens / span if span > 0 else None,
             "req_per_s": len(lat) / span if span > 0 else None,
-            "window_s": span}
+            "window_s": span,
+            "device_ms_per_request": {"generation": gen_ms / max(1, len(ok)),
+                                      "attention": attn_ms / max(1, len(ok))}}
 
 
 def bench_summary(budget_gb=200, n_requests=40):

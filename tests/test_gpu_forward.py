@@ -162,9 +162,10 @@ def test_token_shards_sum_to_the_whole_summary():
 
 def test_generator_matches_host_definition():
     dev = require_gpu()
+    cases = [((2, 3, 64, 16), None, 1.0), ((2, 3, 64, 16), (2, 4, 8), 0.7071067811865476),
+             ((1, 2, 33, 6), None, 1.0)]  # d % 4 != 0: one pair per Philox call
     for dtype, tdt in (("bf16", torch.bfloat16), ("fp32", torch.float32)):
-        for grid, std in ((None, 1.0), ((2, 4, 8), 0.7071067811865476)):
-            shape = (2, 3, 64, 16)
+        for shape, grid, std in cases:
             x = torch.empty(shape, dtype=tdt, device=dev)
             la.gen_fill(x, seed=1234, stream_id=2, std=std, grid=grid)
             torch.cuda.synchronize()
