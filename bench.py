@@ -39,10 +39,14 @@ KERNEL_PASSES = {
     "apply": 2,         # read Q, write O
     "bwd_query": 3,     # read Q, dO; write dQ
     "summary_bwd": 2,   # read Q, dO
+    "bwd_query_ds": 3,  # fused: read Q, dO; write dQ (and the dS, dz partials)
     "bwd_key": 4,       # read K, V; write dK, dV
 }
-# matrix-core FLOPs per launch, in units of 2*B*H*N*d^2
-KERNEL_MMA = {"summary_fwd": 1, "apply": 2, "bwd_query": 2, "summary_bwd": 1, "bwd_key": 2}
+# matrix-core FLOPs per launch, in units of 2*B*H*N*d^2 (the method's
+# products only: S hi + lo counts 2; operand re-layout products are not
+# counted)
+KERNEL_MMA = {"summary_fwd": 1, "apply": 2, "bwd_query": 2, "summary_bwd": 1, "bwd_query_ds": 3,
+              "bwd_key": 2}
 
 
 def parse():
@@ -229,8 +233,11 @@ def main():
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
-    mma_flops = sum(KERNEL_MMA[k] * 2 * elems * w["d"] for k in KERNEL_MMA)
-    step_bytes = sum(KERNEL_PASSES.values()) * elems * 2
+    # what the kernels that ran must move and multiply, per step
+    mma_flops = sum(KERNEL_MMA[k] * kernels[k]["launches_per_step"] * 2 * elems * w["d"]
+                    for k in KERNEL_MMA if k in kernels)
+    step_bytes = sum(KERNEL_PASSES[k] * kernels[k]["launches_per_step"] * elems * 2
+                     for k in KERNEL_PASSES if k in kernels)
     del plan, xs
     torch.cuda.empty_cache()
 

@@ -326,6 +326,275 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 }
 
 // ---------------------------------------------------------------------------
+// Fused query backward (bf16 inputs, d = 32 or 64): dQ exactly as in the
+// query kernel, and in the same pass each wave's partial sums over its own
+// token range [p*Tw, p*Tw + Tw) of
+//   dS = sum_i phi(q_i) (G_i / den_i)^T,   dz = sum_i dden_i phi(q_i),
+// so Q and G are read once.  The reduction contracts over tokens, but the
+// query pass holds one token per lane; the token-major operands are made
+// on the matrix cores themselves: a lane run taken as A[m = token][k =
+// feature] times a 0/1 selection matrix B[k][n] = (k == n + 16h) gives
+// D[token][n] = run feature 32s + 16h + n, i.e. 16 features x 4 tokens in
+// each lane, which is what a contraction over tokens takes.  The whole
+// d x d partial dS stays in registers, so the next step's Q and G are
+// prefetched straight into LDS (global_load_lds, 16 bytes per lane)
+// instead of registers.
+// Partial tile (i, j) holds, in lane (g, n) register r, dS[16i + 4g + r][16j + n]
+// (the combine's block layout); the partial's dz follows at offset d*d.
+// ---------------------------------------------------------------------------
+template <int D>
+struct FusedCfg {
+  using R = Run<D, DT_BF16>;
+  static constexpr int NB = D / 16;                   // 16-feature blocks
+  static constexpr int NS = D / 32;                   // k-steps of a run
+  static constexpr int TT = 2;                        // tiles per step: 32 tokens
+  static constexpr int RW = D / 8;                    // words of a lane's run
+  static constexpr int NCH = R::NCH;                  // 16-byte chunks per run
+  static constexpr int STAGE = TT * 2 * NCH * 1024;   // LDS bytes per wave per step
+  static constexpr int WAVES_PER_SIMD = 2;
+  static constexpr int NSTORE = TT * NCH;             // dQ store instructions per step
+};
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// Wait until at most N vector memory operations of this wave are
+// outstanding (they complete in issue order); also a compiler barrier.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <int OT, int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedCfg<D>::WAVES_PER_SIMD)))
+void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, int64_t sb,
+                    int64_t sh, int64_t sn, void* __restrict__ dq, int64_t osb, int64_t osh,
+                    int64_t osn, int H, int64_t N, int P, int Tw, const void* __restrict__ img,
+                    const double* __restrict__ z64, float* __restrict__ part) {
+  using C = RowCfg<DT_BF16, D>;
+  using FC = FusedCfg<D>;
+  using IC = ImageCfg<D>;
+  using RN = Run<D, DT_BF16>;
+  constexpr int Q4 = D / 4, NT = D / 16, TT = FC::TT, NB = FC::NB, NS = FC::NS;
+  constexpr int RW = FC::RW, NCH = FC::NCH;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int IMG_WORDS = IC::mat_bytes(DT_BF16) / 16;  // the N image
+  constexpr int Z_WORDS = IC::tile_bytes(DT_BF16) / 16;   // the T image's z tile
+  constexpr int E = D * D + D;
+  static_assert(TT == C::TT && RW == C::PW, "run layout");
+  __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
+  __shared__ float zf[D];
+  __shared__ u32x4 stage[4 * FC::STAGE / 16];
+  const u32x4* zimg = simg + IMG_WORDS;
+
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  {
+    const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT_BF16);
+    stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, false);
+    stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT_BF16)), Z_WORDS, false);
+    for (int c = threadIdx.x; c < D; c += 256) zf[c] = (float)z64[(int64_t)bh * D + c];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  const int g = lane >> 4, n = lane & 15;
+  const int p = blockIdx.x * 4 + wave;
+  if (p >= P) return;  // no barriers follow
+  const int64_t t_begin = (int64_t)p * Tw;
+  const int64_t t_end = min(N, t_begin + (int64_t)Tw);
+
+  const int64_t row_bytes = sn * 2, orow_bytes = osn * OES;
+  const char* qh = (const char*)q + (b * sb + h * sh) * 2;
+  const char* gh = (const char*)dout + (b * sb + h * sh) * 2;
+  char* oh = (char*)dq + (b * osb + h * osh) * OES;
+  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
+  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * RN::CH * OES);
+  u32x4* stg = stage + wave * (FC::STAGE / 16);
+
+  // Prefetch a step's Q and G runs into this wave's LDS stage: slot
+  // [(tt*2 + tensor)*NCH + chunk][lane].  Rows past the range are skipped
+  // (their slots keep stale data; the reader zeroes those tokens).
+  auto prefetch = [&](int64_t t0) {
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const bool ok = t0 + 16 * tt + n < t_end;
+#pragma unroll
+      for (int ten = 0; ten < 2; ++ten) {
+        const char* src = (ten == 0 ? qh : gh) + (t0 + 16 * tt) * row_bytes + ioff;
+#pragma unroll
+        for (int w = 0; w < NCH; ++w) {
+          if (ok)
+            __builtin_amdgcn_global_load_lds((const void*)(src + w * 4 * RN::CB),
+                                             (lds_void_ptr)(stg + ((tt * 2 + ten) * NCH + w) * 64),
+                                             16, 0, 0);
+        }
+      }
+    }
+  };
+
+  // 0/1 selection operands: lane (g, n) supplies B[8g + j][n] = (8g + j == n + 16h)
+  bf16x8 sel[2];
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+    uint32_t w4[4] = {0u, 0u, 0u, 0u};
+    const int k = n + 16 * hh;
+    if (k / 8 == g) w4[(k % 8) >> 1] = (k & 1) ? 0x3f800000u : 0x00003f80u;
+    sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
+  }
+
+  f32x4 ds[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) ds[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // dz partial sums: lane (g', n) of block i holds feature 16i + n over the
+  // tokens 4g' + r it saw
+  float dzb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
+
+  prefetch(t_begin);
+  for (int64_t t0 = t_begin; t0 < t_end; t0 += 16 * TT) {
+    // this step's runs: wait for its prefetch (the previous step's dQ
+    // stores may still be in flight), read them, then refill the stage
+    wait_vmem<FC::NSTORE>();
+    uint32_t pq[TT][RW], pg[TT][RW];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      const bool ok = t0 + 16 * tt + n < t_end;
+      uint32_t qw[RW];
+#pragma unroll
+      for (int w = 0; w < NCH; ++w) {
+        const u32x4 a = stg[((tt * 2 + 0) * NCH + w) * 64 + lane];
+        const u32x4 c = stg[((tt * 2 + 1) * NCH + w) * 64 + lane];
+        qw[4 * w] = ok ? a.x : 0u; qw[4 * w + 1] = ok ? a.y : 0u;
+        qw[4 * w + 2] = ok ? a.z : 0u; qw[4 * w + 3] = ok ? a.w : 0u;
+        pg[tt][4 * w] = ok ? c.x : 0u; pg[tt][4 * w + 1] = ok ? c.y : 0u;
+        pg[tt][4 * w + 2] = ok ? c.z : 0u; pg[tt][4 * w + 3] = ok ? c.w : 0u;
+      }
+      phi_words<DT_BF16, D>(qw, pq[tt]);
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (t0 + 16 * TT < t_end) prefetch(t0 + 16 * TT);
+
+    // X = S G and den = phi(q) . z on the matrix cores
+    f32x4 acc[TT][NT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+      for (int i = 0; i < NT; ++i) acc[tt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    image_times_runs<DT_BF16, D, true>(simg, lane, pg, acc);
+    f32x4 dacc[TT][1];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) dacc[tt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+    tile_times_runs<DT_BF16, D>(zimg, lane, pq, dacc);
+
+    // token-major G operands for dS: bg[j] = G of feature block j, 8 tokens
+    bf16x8 bg[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      f32x4 tr[TT];
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        const int s0 = j >> 1;
+        const bf16x8 a = as_bf16x8(u32x4{pg[tt][4 * s0], pg[tt][4 * s0 + 1], pg[tt][4 * s0 + 2],
+                                         pg[tt][4 * s0 + 3]});
+        tr[tt] = mfma_bf16(a, sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
+      }
+      // exact: the products are bf16 values times 1
+      bg[j] = as_bf16x8(u32x4{pack_bf16(tr[0][0], tr[0][1]), pack_bf16(tr[0][2], tr[0][3]),
+                              pack_bf16(tr[1][0], tr[1][1]), pack_bf16(tr[1][2], tr[1][3])});
+    }
+
+    // per token: den, G . O, dQ, and the scales 1/den and dden = -(G . O)/den
+    float rdt[TT], ddt[TT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      float gn = 0.f;
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq[tt], 4 * i + r) * acc[tt][i][r];
+      gn = sum_groups(gn);
+      const double rden = 1.0 / (double)dacc[tt][0][0];
+      const float rd = (float)rden;
+      const float go = gn * rd;  // G . O
+      rdt[tt] = rd;
+      ddt[tt] = -go * rd;        // zero for padded tokens (G = 0)
+      const int64_t t = t0 + 16 * tt + n;
+      const bool ok = t < t_end;
+      // dQ chunk by chunk (few live registers): run positions [CH*w, +CH)
+      constexpr int CH = RN::CH;
+      constexpr int OCB = CH * OES;
+      char* orow = oh + (t0 + 16 * tt) * orow_bytes + ooff;
+#pragma unroll
+      for (int w = 0; w < NCH; ++w) {
+        uint32_t ow[OCB / 4];
+#pragma unroll
+        for (int j = 0; j < CH; j += 2) {
+          float o2[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int c = CH * w + j + u;
+            const float ph = run_val<DT_BF16>(pq[tt], c);
+            const float zc = zf[RN::feature(g, c)];
+            o2[u] = (fmaf(-go, zc, acc[tt][c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
+          }
+          if constexpr (OT == DT_BF16) {
+            ow[j >> 1] = pack_bf16(o2[0], o2[1]);
+          } else {
+            ow[j] = __float_as_uint(o2[0]);
+            ow[j + 1] = __float_as_uint(o2[1]);
+          }
+        }
+        if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
+      }
+    }
+
+    // dS[i][j] += (phi(q)/den of block i, token-major) x bg[j], and
+    // dz[block i] += token sums of phi(q) dden, both made token-major by
+    // the selection product
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int s0 = i >> 1;
+      f32x4 tr[TT], tz[TT];
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt) {
+        uint32_t wa[4], wz[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t w = pq[tt][4 * s0 + k];
+          wa[k] = pack_bf16(bf16lo(w) * rdt[tt], bf16hi(w) * rdt[tt]);
+          wz[k] = pack_bf16(bf16lo(w) * ddt[tt], bf16hi(w) * ddt[tt]);
+        }
+        tr[tt] = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
+                           f32x4{0.f, 0.f, 0.f, 0.f});
+        tz[tt] = mfma_bf16(as_bf16x8(u32x4{wz[0], wz[1], wz[2], wz[3]}), sel[i & 1],
+                           f32x4{0.f, 0.f, 0.f, 0.f});
+      }
+      dzb[i] += ((tz[0][0] + tz[0][1]) + (tz[0][2] + tz[0][3])) +
+                ((tz[1][0] + tz[1][1]) + (tz[1][2] + tz[1][3]));
+      const bf16x8 ai = as_bf16x8(u32x4{pack_bf16(tr[0][0], tr[0][1]), pack_bf16(tr[0][2], tr[0][3]),
+                                        pack_bf16(tr[1][0], tr[1][1]), pack_bf16(tr[1][2], tr[1][3])});
+#pragma unroll
+      for (int j = 0; j < NB; ++j) ds[i][j] = mfma_bf16(ai, bg[j], ds[i][j]);
+    }
+  }
+
+  // the wave's partial: dS tiles in lane order, then dz
+  float* out = part + ((int64_t)bh * P + p) * E;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) *(f32x4*)(out + ((i * NB + j) * 64 + lane) * 4) = ds[i][j];
+  // dz: add the four lane groups' token subsets
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const float v = sum_groups(dzb[i]);
+    if (g == 0) out[D * D + 16 * i + n] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Key kernel: dV = phi(K) dS (T image of dS) and dK = (V dS^T + dz) phi'(K)
 // (N image of dS).  WHICH: 1 = dV only, 2 = dK only, 3 = both.
 // The dS operands are the hi parts of the bf16 images.
@@ -468,15 +737,27 @@ template <int DT, int OT, int D>
 static void launch_rows(const BwdArgs& a) {
   const int BH = (int)(a.B * a.H);
   dim3 grid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
-  {
-    ProfScope prof("bwd_query", a.stream);
-    bwd_query_kernel<DT, OT, D><<<grid, 256, 0, a.stream>>>(
-        a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img,
-        a.z64, a.stash);
+  if constexpr (DT == DT_BF16 && (D == 32 || D == 64)) {
+    // one pass: dQ and the per-wave partials of dS, dz (at d = 128 the
+    // whole partial dS plus the query pass's state exceed the registers of
+    // one wave, and the two-pass form is faster)
+    ProfScope prof("bwd_query_ds", a.stream);
+    dim3 fgrid((unsigned)((a.P + 3) / 4), BH);
+    bwd_qds_kernel<OT, D><<<fgrid, 256, 0, a.stream>>>(
+        a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
+        a.img, a.z64, a.part);
+    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
+  } else {
+    {
+      ProfScope prof("bwd_query", a.stream);
+      bwd_query_kernel<DT, OT, D><<<grid, 256, 0, a.stream>>>(
+          a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img,
+          a.z64, a.stash);
+    }
+    launch_summary(MODE_BWD, DT, D, a.q, a.dout, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
+                   a.stash, a.part, a.stream);
+    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_SUMMARY, a.stream);
   }
-  launch_summary(MODE_BWD, DT, D, a.q, a.dout, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
-                 a.stash, a.part, a.stream);
-  launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, a.stream);
   // both dS images fit in LDS except fp32 at d = 128 (2 x 64 KB): two passes
   ProfScope prof("bwd_key", a.stream);
   if constexpr (DT == DT_FP32 && D >= 128) {

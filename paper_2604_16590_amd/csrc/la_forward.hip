@@ -318,7 +318,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SummaryCfg<
 // results are bitwise reproducible), writing the dense FP64 matrix M
 // (S or dS) and vector (z or dz), plus the matrix-core operand images.
 // ---------------------------------------------------------------------------
-template <int D>
+// Partial layouts: PART_SUMMARY (the summary kernel's tiles: tile (i, j),
+// lane (g, n), register r holds M[F(4g + r) + i][F n + j], F = d/16) and
+// PART_BLOCKS (the fused query backward's: M[16i + 4g + r][16j + n]).
+template <int D, int LAYOUT>
 __global__ __launch_bounds__(256) void combine_kernel(
     const float* __restrict__ part, int P, double* __restrict__ M64,
     double* __restrict__ v64, void* __restrict__ img, int img_dt) {
@@ -334,7 +337,8 @@ __global__ __launch_bounds__(256) void combine_kernel(
     const int r = u & 3, lane = (u >> 2) & 63, ij = u >> 8;
     const int i = ij / F, j = ij % F;
     const int g = lane >> 4, n = lane & 15;
-    const int c = F * (4 * g + r) + i, e = F * n + j;
+    const int c = LAYOUT == PART_SUMMARY ? F * (4 * g + r) + i : 16 * i + 4 * g + r;
+    const int e = LAYOUT == PART_SUMMARY ? F * n + j : 16 * j + n;
     M64[(int64_t)bh * D * D + c * D + e] = s;
     write_images<D>(img, img_dt, bh, c, e, s);
   } else {
@@ -578,15 +582,24 @@ hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v,
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
-                          int img_dt, int64_t BH, int D, hipStream_t stream) {
+template <int D>
+static void launch_combine_d(const float* part, int P, double* M64, double* v64, void* img,
+                             int img_dt, int64_t BH, int layout, hipStream_t stream) {
   dim3 grid((D * D + D + 255) / 256, (unsigned)BH);
+  if (layout == PART_SUMMARY)
+    combine_kernel<D, PART_SUMMARY><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt);
+  else
+    combine_kernel<D, PART_BLOCKS><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt);
+}
+
+hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
+                          int img_dt, int64_t BH, int D, int layout, hipStream_t stream) {
   ProfScope prof("combine", stream);
   switch (D) {
-    case 16: combine_kernel<16><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
-    case 32: combine_kernel<32><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
-    case 64: combine_kernel<64><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
-    case 128: combine_kernel<128><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt); break;
+    case 16: launch_combine_d<16>(part, P, M64, v64, img, img_dt, BH, layout, stream); break;
+    case 32: launch_combine_d<32>(part, P, M64, v64, img, img_dt, BH, layout, stream); break;
+    case 64: launch_combine_d<64>(part, P, M64, v64, img, img_dt, BH, layout, stream); break;
+    case 128: launch_combine_d<128>(part, P, M64, v64, img, img_dt, BH, layout, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -603,7 +616,8 @@ static hipError_t launch_forward_d(const FwdArgs& a) {
   {
     dim3 cgrid((D * D + D + 255) / 256, BH);
     ProfScope prof("combine", a.stream);
-    combine_kernel<D><<<cgrid, 256, 0, a.stream>>>(a.part, a.P, a.S64, a.z64, a.img, a.in_dt);
+    combine_kernel<D, PART_SUMMARY><<<cgrid, 256, 0, a.stream>>>(a.part, a.P, a.S64, a.z64, a.img,
+                                                                 a.in_dt);
   }
   return launch_apply_only<D>(a);
 }

@@ -198,6 +198,7 @@ struct BwdArgs {
 };
 
 enum { MODE_FWD = 0, MODE_BWD = 1 };
+enum { PART_SUMMARY = 0, PART_BLOCKS = 1 };  // layouts of per-wave partial sums
 
 hipError_t launch_forward(const FwdArgs& a);
 // Apply only: images of a given S (into a.img), then the apply kernel.
@@ -208,7 +209,7 @@ hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v,
                           int64_t sh, int64_t sn, int64_t B, int64_t H, int64_t N, int P,
                           int Tw, const float2* stash, float* part, hipStream_t stream);
 hipError_t launch_combine(const float* part, int P, double* M64, double* v64, void* img,
-                          int img_dt, int64_t BH, int D, hipStream_t stream);
+                          int img_dt, int64_t BH, int D, int layout, hipStream_t stream);
 hipError_t launch_backward(const BwdArgs& a);
 // Images (both, with the z tile) of a given M and v.
 hipError_t launch_images(const double* M64, const double* v64, void* img, int img_dt, int64_t BH,
