@@ -62,7 +62,9 @@ Tiling choose_tiling(int64_t N, int d) {
   const int64_t tw_min = d >= 128 ? 2048 : 1024;
   const int64_t p_max = 128;
   int64_t P = std::min<int64_t>(p_max, ceil_div(N, tw_min));
-  int64_t Tw = ceil_div(ceil_div(N, P), 32) * 32;
+  // a multiple of 64: the summary steps over 32 tokens, the fused
+  // backward over 64 (four waves x 16)
+  int64_t Tw = ceil_div(ceil_div(N, P), 64) * 64;
   P = ceil_div(N, Tw);
   Tiling t;
   t.P = (int)P;

@@ -174,7 +174,7 @@ __device__ __forceinline__ void tile_times_runs(
 // Copy `words` 16-byte words of an image into LDS; with `hi_only` only the
 // hi half of each (tile, k-step) pair of a bf16 image is kept.
 __device__ __forceinline__ void stage_image(u32x4* dst, const u32x4* src, int words, bool hi_only) {
-  for (int w = threadIdx.x; w < words; w += 256) {
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
     if (hi_only) {
       const int pair = w >> 6, lane = w & 63;
       dst[w] = src[pair * 128 + lane];
@@ -595,6 +595,220 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 }
 
 // ---------------------------------------------------------------------------
+// Fused query backward at d = 128 (bf16): the eight waves of a workgroup
+// (two per SIMD) share one partial (token range [p*Tw, p*Tw + Tw)), taking
+// 16-token tiles in turn (128 tokens per step).  Each wave does the query
+// pass for its tile and makes its tile's token-major operands (as in
+// bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
+// accumulates the dS row block w over all eight tiles (four 32-token
+// contractions), so its share of the partial is 8 tiles (32 registers)
+// instead of the whole 128 x 128.  dz is summed per wave and added across
+// the waves at the end.
+// ---------------------------------------------------------------------------
+template <int OT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, int64_t sb,
+                     int64_t sh, int64_t sn, void* __restrict__ dq, int64_t osb, int64_t osh,
+                     int64_t osn, int H, int64_t N, int P, int Tw, const void* __restrict__ img,
+                     const double* __restrict__ z64, float* __restrict__ part) {
+  constexpr int D = 128;
+  using IC = ImageCfg<D>;
+  using RN = Run<D, DT_BF16>;
+  constexpr int Q4 = D / 4, NT = D / 16, NB = D / 16, NS = IC::NS;
+  constexpr int RW = D / 8, NCH = RN::NCH, CH = RN::CH;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int OCB = CH * OES;
+  constexpr int IMG_WORDS = IC::mat_bytes(DT_BF16) / 16;  // the N image
+  constexpr int Z_WORDS = IC::tile_bytes(DT_BF16) / 16;   // the T image's z tile
+  constexpr int E = D * D + D;
+  __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
+  __shared__ float zf[D];
+  constexpr int NW = 8;             // waves (tiles per step)
+  __shared__ u32x2 xa[NW][NB][64];  // per tile and block: phi(q)/den, 4 tokens per lane (bf16)
+  __shared__ u32x2 xb[NW][NB][64];  // the same for G
+  __shared__ float dzs[NW][D];
+  const u32x4* zimg = simg + IMG_WORDS;
+
+  const int bh = blockIdx.y;
+  const int64_t b = bh / H, h = bh % H;
+  {
+    const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT_BF16);
+    stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, false);
+    stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT_BF16)), Z_WORDS, false);
+    for (int c = threadIdx.x; c < D; c += 512) zf[c] = (float)z64[(int64_t)bh * D + c];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  const int g = lane >> 4, n = lane & 15;
+  const int p = blockIdx.x;
+  const int64_t t_begin = (int64_t)p * Tw;
+  const int64_t t_end = min(N, t_begin + (int64_t)Tw);
+  const int nsteps = (int)((t_end - t_begin + 16 * NW - 1) / (16 * NW));  // the same for all waves
+
+  const int64_t row_bytes = sn * 2, orow_bytes = osn * OES;
+  const char* qh = (const char*)q + (b * sb + h * sh) * 2;
+  const char* gh = (const char*)dout + (b * sb + h * sh) * 2;
+  char* oh = (char*)dq + (b * osb + h * osh) * OES;
+  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
+  const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OCB);
+
+  typedef uint32_t Regs[2][RW];  // Q run, G run of this wave's tile
+  auto load = [&](int k, Regs& x) {
+    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
+    if (tb + n < t_end) {
+      load_run<D, DT_BF16>(qh + tb * row_bytes + ioff, x[0]);
+      load_run<D, DT_BF16>(gh + tb * row_bytes + ioff, x[1]);
+    } else {
+#pragma unroll
+      for (int w = 0; w < RW; ++w) { x[0][w] = 0u; x[1][w] = 0u; }
+    }
+  };
+
+  bf16x8 sel[2];
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+    uint32_t w4[4] = {0u, 0u, 0u, 0u};
+    const int k = n + 16 * hh;
+    if (k / 8 == g) w4[(k % 8) >> 1] = (k & 1) ? 0x3f800000u : 0x00003f80u;
+    sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
+  }
+
+  f32x4 ds[NB];  // rows of block `wave`
+#pragma unroll
+  for (int j = 0; j < NB; ++j) ds[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dzb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
+
+  auto step = [&](int k, const Regs& x) {
+    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
+    uint32_t pq[RW];
+    phi_words<DT_BF16, D>(x[0], pq);
+    const uint32_t* pg = x[1];
+    // X = S G (hi + lo) and den = phi(q) . z (z tile) for the tile
+    f32x4 acc[NT], dacc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const bf16x8 bt = as_bf16x8(u32x4{pg[4 * s], pg[4 * s + 1], pg[4 * s + 2], pg[4 * s + 3]});
+        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]), bt, acc[i]);
+        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]), bt, acc[i]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bf16x8 bt = as_bf16x8(u32x4{pq[4 * s], pq[4 * s + 1], pq[4 * s + 2], pq[4 * s + 3]});
+      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 0) * 64 + lane]), bt, dacc);
+      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 1) * 64 + lane]), bt, dacc);
+    }
+    // token-major G of this tile into LDS
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s0 = j >> 1;
+      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{pg[4 * s0], pg[4 * s0 + 1], pg[4 * s0 + 2], pg[4 * s0 + 3]}),
+                                 sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
+      xb[wave][j][lane] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+    }
+    // per token: G . O, dQ, scales
+    float gn = 0.f;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq, 4 * i + r) * acc[i][r];
+    gn = sum_groups(gn);
+    const double rden = 1.0 / (double)dacc[0];
+    const float rd = (float)rden;
+    const float go = gn * rd;
+    const float dd = -go * rd;  // dden; zero for padded tokens (G = 0)
+    const bool ok = tb + n < t_end;
+    char* orow = oh + tb * orow_bytes + ooff;
+#pragma unroll
+    for (int w = 0; w < NCH; ++w) {
+      uint32_t ow[OCB / 4];
+#pragma unroll
+      for (int j = 0; j < CH; j += 2) {
+        float o2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int c = CH * w + j + u;
+          const float ph = run_val<DT_BF16>(pq, c);
+          o2[u] = (fmaf(-go, zf[RN::feature(g, c)], acc[c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
+        }
+        if constexpr (OT == DT_BF16) {
+          ow[j >> 1] = pack_bf16(o2[0], o2[1]);
+        } else {
+          ow[j] = __float_as_uint(o2[0]);
+          ow[j + 1] = __float_as_uint(o2[1]);
+        }
+      }
+      if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
+    }
+    // token-major phi(q)/den into LDS; dz over this tile's tokens
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int s0 = i >> 1;
+      uint32_t wa[4], wz[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t w = pq[4 * s0 + kk];
+        wa[kk] = pack_bf16(bf16lo(w) * rd, bf16hi(w) * rd);
+        wz[kk] = pack_bf16(bf16lo(w) * dd, bf16hi(w) * dd);
+      }
+      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
+                                 f32x4{0.f, 0.f, 0.f, 0.f});
+      const f32x4 tz = mfma_bf16(as_bf16x8(u32x4{wz[0], wz[1], wz[2], wz[3]}), sel[i & 1],
+                                 f32x4{0.f, 0.f, 0.f, 0.f});
+      xa[wave][i][lane] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+      dzb[i] += (tz[0] + tz[1]) + (tz[2] + tz[3]);
+    }
+    __syncthreads();
+    // dS rows of block `wave` over the eight tiles: tiles (2k, 2k + 1)
+    // make one 32-token contraction
+#pragma unroll
+    for (int kap = 0; kap < NW / 2; ++kap) {
+      const u32x2 alo = xa[2 * kap][wave][lane], ahi = xa[2 * kap + 1][wave][lane];
+      const bf16x8 aa = as_bf16x8(u32x4{alo.x, alo.y, ahi.x, ahi.y});
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const u32x2 lo = xb[2 * kap][j][lane], hi = xb[2 * kap + 1][j][lane];
+        ds[j] = mfma_bf16(aa, as_bf16x8(u32x4{lo.x, lo.y, hi.x, hi.y}), ds[j]);
+      }
+    }
+    __syncthreads();  // before the next step rewrites xa, xb
+  };
+
+  Regs ra, rb;
+  load(0, ra);
+  for (int k = 0; k < nsteps; k += 2) {
+    if (k + 1 < nsteps) load(k + 1, rb);
+    step(k, ra);
+    if (k + 1 >= nsteps) break;
+    if (k + 2 < nsteps) load(k + 2, ra);
+    step(k + 1, rb);
+  }
+
+  // the workgroup's partial: this wave's row blocks, then dz over all waves
+  float* out = part + ((int64_t)bh * P + p) * E;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) *(f32x4*)(out + ((wave * NB + j) * 64 + lane) * 4) = ds[j];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const float v = sum_groups(dzb[i]);
+    if (g == 0) dzs[wave][16 * i + n] = v;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < D; c += 512) {
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += dzs[w][c];
+    out[D * D + c] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Key kernel: dV = phi(K) dS (T image of dS) and dK = (V dS^T + dz) phi'(K)
 // (N image of dS).  WHICH: 1 = dV only, 2 = dK only, 3 = both.
 // The dS operands are the hi parts of the bf16 images.
@@ -737,7 +951,15 @@ template <int DT, int OT, int D>
 static void launch_rows(const BwdArgs& a) {
   const int BH = (int)(a.B * a.H);
   dim3 grid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
-  if constexpr (DT == DT_BF16 && (D == 32 || D == 64)) {
+  if constexpr (DT == DT_BF16 && D == 128) {
+    // one pass, eight waves sharing each partial
+    ProfScope prof("bwd_query_ds", a.stream);
+    dim3 fgrid((unsigned)a.P, BH);
+    bwd_qds4_kernel<OT><<<fgrid, 512, 0, a.stream>>>(
+        a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
+        a.img, a.z64, a.part);
+    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
+  } else if constexpr (DT == DT_BF16 && (D == 32 || D == 64)) {
     // one pass: dQ and the per-wave partials of dS, dz (at d = 128 the
     // whole partial dS plus the query pass's state exceed the registers of
     // one wave, and the two-pass form is faster)
