@@ -676,9 +676,9 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   f32x4 ds[NB];  // rows of block `wave`
 #pragma unroll
   for (int j = 0; j < NB; ++j) ds[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dzb[NB];
+  float zacc[Q4];  // dz partial sums per run position over this wave's tokens
 #pragma unroll
-  for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
+  for (int c = 0; c < Q4; ++c) zacc[c] = 0.f;
 
   auto step = [&](int k, const Regs& x) {
     const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
@@ -746,23 +746,22 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       }
       if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
     }
-    // token-major phi(q)/den into LDS; dz over this tile's tokens
+    // dz += dden phi(q) (per lane, this lane's token)
+#pragma unroll
+    for (int c = 0; c < Q4; ++c) zacc[c] = fmaf(dd, run_val<DT_BF16>(pq, c), zacc[c]);
+    // token-major phi(q)/den into LDS
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int s0 = i >> 1;
-      uint32_t wa[4], wz[4];
+      uint32_t wa[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const uint32_t w = pq[4 * s0 + kk];
         wa[kk] = pack_bf16(bf16lo(w) * rd, bf16hi(w) * rd);
-        wz[kk] = pack_bf16(bf16lo(w) * dd, bf16hi(w) * dd);
       }
       const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
                                  f32x4{0.f, 0.f, 0.f, 0.f});
-      const f32x4 tz = mfma_bf16(as_bf16x8(u32x4{wz[0], wz[1], wz[2], wz[3]}), sel[i & 1],
-                                 f32x4{0.f, 0.f, 0.f, 0.f});
       xa[wave][i][lane] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
-      dzb[i] += (tz[0] + tz[1]) + (tz[2] + tz[3]);
     }
     __syncthreads();
     // dS rows of block `wave` over the eight tiles: tiles (2k, 2k + 1)
@@ -794,10 +793,15 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   float* out = part + ((int64_t)bh * P + p) * E;
 #pragma unroll
   for (int j = 0; j < NB; ++j) *(f32x4*)(out + ((wave * NB + j) * 64 + lane) * 4) = ds[j];
+  // dz: each run position summed over the 16 tokens (lanes n) of the group
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const float v = sum_groups(dzb[i]);
-    if (g == 0) dzs[wave][16 * i + n] = v;
+  for (int c = 0; c < Q4; ++c) {
+    float v = zacc[c];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    if (n == 0) dzs[wave][RN::feature(g, c)] = v;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < D; c += 512) {
