@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--cpu-tokens", type=int, default=65536,
+    ap.add_argument("--no-others", action="store_true", help="skip the other workload shapes")
+    ap.add_argument("--cpu-tokens", type=int, default=262144,
                     help="tokens per head of the oracle sample (8 heads, d = 128)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
@@ -133,6 +134,44 @@ def traffic_for(kernel):
     return k.get("hbm_bytes_per_launch")
 
 
+def other_workloads(steps):
+    """tokens/s of the same path at the task's other bf16 shapes: the
+    fwd+bwd shape at d = 64 (B2 H16, T64 x 64 x 64 = 262,144 tokens) and the
+    grid forward (B4 H16, T8 x 32 x 64 = 16,384 tokens, d = 64)."""
+    import torch
+    import paper_2604_16590_amd as la
+    out = {}
+    for name, (B, H, N, d), bwd in (("fwd_bwd_B2_H16_N262144_d64", (2, 16, 262144, 64), True),
+                                    ("fwd_B4_H16_N16384_d64", (4, 16, 16384, 64), False)):
+        xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device="cuda:0") for _ in range(4)]
+        for sid, x in enumerate(xs):
+            la.gen_fill(x, seed=1001, stream_id=sid)
+        plan = la.Plan(*xs[:3], dout=xs[3])
+
+        def step():
+            plan.forward()
+            if bwd:
+                plan.backward()
+
+        t = time_steps(step, max(steps, 20), 3)
+        out[name] = {"tokens_per_s": round(B * N / t, 1), "ms_per_step": round(t * 1e3, 4)}
+        log("%s %.3f ms" % (name, t * 1e3))
+        del plan, xs
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n_tokens):
     """The FP64 oracle (as it stands) on a bounded sample of the workload:
     B1 H8 n_tokens d128 bf16, forward + backward; also the GPU's normwise
@@ -169,7 +208,7 @@ def cpu_baseline(n_tokens):
               "dv": err(plan.dv, dv_r)}
     return {
         "value": round(n_tokens / dt, 1), "unit": "tokens/s", "cores": oracle.threads(),
-        "kind": "oracle",
+        "kind": "oracle", "cpu": cpu_model(),
         "sample": "fwd+bwd, B1 H8 N%d d128 bf16 N(0,0.5) inputs, FP64 oracle, %.1f s" % (n_tokens, dt),
     }, errors
 
@@ -241,6 +280,13 @@ def main():
     del plan, xs
     torch.cuda.empty_cache()
 
+    peak_bytes = torch.cuda.max_memory_allocated()
+
+    # ---- the other workload shapes (context for the same kernels) ----
+    others = None
+    if not args.no_others:
+        others = other_workloads(args.steps)
+
     # ---- fp32: the same step in plain fp32 ----
     fp32 = None
     if not args.no_fp32:
@@ -304,6 +350,8 @@ def main():
         "step_mma_TFLOP_s": round(mma_flops / t_step / 1e12, 2),
         "roofline": roofline,
         "kernels": kernels,
+        "peak_device_bytes": peak_bytes,
+        "other_workloads": others,
         "fp32": fp32,
         "serve": serve,
         "cpu_baseline": cpu,

@@ -188,6 +188,7 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
             "failed": sum(1 for x in done if x[2] == FAILED),
             "offered_req_per_s": rate_per_s,
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "p999_ms": percentile(lat, 99.9),
             "max_ms": max(lat) if lat else None,
             "tokens_per_s": tokens / span if span > 0 else None,
             "req_per_s": len(lat) / span if span > 0 else None,
