@@ -91,6 +91,45 @@ def test_autograd_with_strided_inputs_and_fp32():
         assert normwise(as64(x.contiguous()), r) < TOL["fp32"]
 
 
+@pytest.mark.parametrize("d", [32, 64, 128])
+def test_strided_bnhd_bf16_backward(d):
+    # bf16 takes the fused query pass at these head dims; inputs are views
+    # of [B, N, H, d] buffers (token stride H*d), gradients contiguous
+    dev = require_gpu()
+    B, N, H = 2, 1300, 3
+    q, k, v, g = make_inputs((B, N, H, d), "bf16", 40 + d, streams=(0, 1, 2, 3))
+    tq, tk, tv, tg = (to_device(x, dev).permute(0, 2, 1, 3) for x in (q, k, v, g))
+    print("case strided bnhd bf16", B, N, H, d, flush=True)
+    _, S, z = la.forward(tq, tk, tv, return_summary=True)
+    dq, dk, dv = la.backward(tq, tk, tv, S, z, tg)
+    torch.cuda.synchronize()
+    perm = lambda a: np.ascontiguousarray(a.transpose(0, 2, 1, 3))
+    rq, rk, rv = oracle.backward(perm(q), perm(k), perm(v), perm(g))
+    for name, x, r in (("dq", dq, rq), ("dk", dk, rk), ("dv", dv, rv)):
+        err = normwise(as64(x), r)
+        assert err < TOL["bf16"], (name, err)
+
+
+def test_constant_values_bf16_fused_pass():
+    # constant V: dQ and dK vanish exactly; the fused pass's dS and dz
+    # must cancel in dK = (dS v + dz) phi'(k) just as the two-pass ones do
+    from paper_2604_16590_amd import inputs
+    dev = require_gpu()
+    for d in (64, 128):
+        shape = (1, 2, 3000, d)
+        q, k, _, g = make_inputs(shape, "bf16", 41, streams=(0, 1, 2, 3))
+        row = inputs.generate(inputs.GenSpec(seed=41, stream=9), (1, 1, 1, d), "bf16")
+        v = np.ascontiguousarray(np.broadcast_to(row, shape))
+        print("case constant V bf16", shape, flush=True)
+        dq, dk, dv = gpu_grads(q, k, v, g)
+        rq, rk, rv = oracle.backward(q, k, v, g)
+        # relative to the size of the terms that cancel (|dV| |v|)
+        scale = np.abs(as64(dv)).max() * np.abs(as64(v)).max()
+        assert np.abs(as64(dq)).max() < TOL["bf16"] * scale
+        assert np.abs(as64(dk)).max() < TOL["bf16"] * scale
+        assert normwise(as64(dv), rv) < TOL["bf16"]
+
+
 def test_value_gradient_column_sums_equal_upstream_sums():
     q, k, v, g = make_inputs((1, 2, 30000, 64), "fp32", 36, streams=(0, 1, 2, 3))
     dq, dk, dv = gpu_grads(q, k, v, g)
