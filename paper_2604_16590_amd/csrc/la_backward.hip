@@ -624,8 +624,11 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
   __shared__ float zf[D];
   constexpr int NW = 8;             // waves (tiles per step)
-  __shared__ u32x2 xa[NW][NB][64];  // per tile and block: phi(q)/den, 4 tokens per lane (bf16)
-  __shared__ u32x2 xb[NW][NB][64];  // the same for G
+  // token-major operands of a 32-token contraction: tiles 2*kap and
+  // 2*kap + 1 write the low and high halves of one 16-byte slot per lane,
+  // so a slot is one operand (one LDS read)
+  __shared__ u32x4 xa[NW / 2][NB][64];  // phi(q)/den of block i
+  __shared__ u32x4 xb[NW / 2][NB][64];  // G of block j
   __shared__ float dzs[NW][D];
   const u32x4* zimg = simg + IMG_WORDS;
 
@@ -710,7 +713,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       const int s0 = j >> 1;
       const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{pg[4 * s0], pg[4 * s0 + 1], pg[4 * s0 + 2], pg[4 * s0 + 3]}),
                                  sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
-      xb[wave][j][lane] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+      ((u32x2*)&xb[wave >> 1][j][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     // per token: G . O, dQ, scales
     float gn = 0.f;
@@ -761,20 +764,16 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       }
       const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
                                  f32x4{0.f, 0.f, 0.f, 0.f});
-      xa[wave][i][lane] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+      ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     __syncthreads();
     // dS rows of block `wave` over the eight tiles: tiles (2k, 2k + 1)
     // make one 32-token contraction
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
-      const u32x2 alo = xa[2 * kap][wave][lane], ahi = xa[2 * kap + 1][wave][lane];
-      const bf16x8 aa = as_bf16x8(u32x4{alo.x, alo.y, ahi.x, ahi.y});
+      const bf16x8 aa = as_bf16x8(xa[kap][wave][lane]);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const u32x2 lo = xb[2 * kap][j][lane], hi = xb[2 * kap + 1][j][lane];
-        ds[j] = mfma_bf16(aa, as_bf16x8(u32x4{lo.x, lo.y, hi.x, hi.y}), ds[j]);
-      }
+      for (int j = 0; j < NB; ++j) ds[j] = mfma_bf16(aa, as_bf16x8(xb[kap][j][lane]), ds[j]);
     }
     __syncthreads();  // before the next step rewrites xa, xb
   };
