@@ -595,27 +595,18 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 }
 
 // ---------------------------------------------------------------------------
-// Fused query backward at d = 128 (bf16): the NW waves of a workgroup share
-// one partial (token range [p*Tw, p*Tw + Tw)), each taking TW 16-token
-// tiles per step (16*NW*TW tokens per step).  Each wave does the query
-// pass for its tiles and makes their token-major operands (as in
+// Fused query backward at d = 128 (bf16): the eight waves of a workgroup
+// (two per SIMD) share one partial (token range [p*Tw, p*Tw + Tw)), taking
+// 16-token tiles in turn (128 tokens per step).  Each wave does the query
+// pass for its tile and makes its tile's token-major operands (as in
 // bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
-// accumulates its NB/NW row blocks of dS over all the step's tiles
-// (32-token contractions over tile pairs), so its share of the partial is
-// (NB/NW)*NB tiles instead of the whole 128 x 128.  dz is summed per lane
-// and added across the waves at the end.
+// accumulates the dS row block w over all eight tiles (four 32-token
+// contractions), so its share of the partial is 8 tiles (32 registers)
+// instead of the whole 128 x 128.  dz is summed per wave and added across
+// the waves at the end.
 // ---------------------------------------------------------------------------
-template <int NW, int TW>
-struct Fused4Cfg {
-  static constexpr int THREADS = 64 * NW;
-  static constexpr int WAVES_PER_SIMD = NW / 4;
-  static constexpr int TILES = NW * TW;   // per step
-  static constexpr int KAPS = TILES / 2;  // 32-token contractions per step
-  static constexpr int RB = 8 / NW;       // dS row blocks per wave
-};
-
-template <int OT, int NW, int TW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)))
+template <int OT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, int64_t sb,
                      int64_t sh, int64_t sn, void* __restrict__ dq, int64_t osb, int64_t osh,
                      int64_t osn, int H, int64_t N, int P, int Tw, const void* __restrict__ img,
@@ -623,7 +614,6 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   constexpr int D = 128;
   using IC = ImageCfg<D>;
   using RN = Run<D, DT_BF16>;
-  using FC = Fused4Cfg<NW, TW>;
   constexpr int Q4 = D / 4, NT = D / 16, NB = D / 16, NS = IC::NS;
   constexpr int RW = D / 8, NCH = RN::NCH, CH = RN::CH;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
@@ -631,14 +621,14 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   constexpr int IMG_WORDS = IC::mat_bytes(DT_BF16) / 16;  // the N image
   constexpr int Z_WORDS = IC::tile_bytes(DT_BF16) / 16;   // the T image's z tile
   constexpr int E = D * D + D;
-  constexpr int RB = FC::RB, KAPS = FC::KAPS;
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
   __shared__ float zf[D];
+  constexpr int NW = 8;             // waves (tiles per step)
   // token-major operands of a 32-token contraction: tiles 2*kap and
   // 2*kap + 1 write the low and high halves of one 16-byte slot per lane,
   // so a slot is one operand (one LDS read)
-  __shared__ u32x4 xa[KAPS][NB][64];  // phi(q)/den of block i
-  __shared__ u32x4 xb[KAPS][NB][64];  // G of block j
+  __shared__ u32x4 xa[NW / 2][NB][64];  // phi(q)/den of block i
+  __shared__ u32x4 xb[NW / 2][NB][64];  // G of block j
   __shared__ float dzs[NW][D];
   const u32x4* zimg = simg + IMG_WORDS;
 
@@ -648,7 +638,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT_BF16);
     stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, false);
     stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT_BF16)), Z_WORDS, false);
-    for (int c = threadIdx.x; c < D; c += FC::THREADS) zf[c] = (float)z64[(int64_t)bh * D + c];
+    for (int c = threadIdx.x; c < D; c += 512) zf[c] = (float)z64[(int64_t)bh * D + c];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = wave_index();
@@ -656,8 +646,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   const int p = blockIdx.x;
   const int64_t t_begin = (int64_t)p * Tw;
   const int64_t t_end = min(N, t_begin + (int64_t)Tw);
-  constexpr int STEP = 16 * FC::TILES;
-  const int nsteps = (int)((t_end - t_begin + STEP - 1) / STEP);  // the same for all waves
+  const int nsteps = (int)((t_end - t_begin + 16 * NW - 1) / (16 * NW));  // the same for all waves
 
   const int64_t row_bytes = sn * 2, orow_bytes = osn * OES;
   const char* qh = (const char*)q + (b * sb + h * sh) * 2;
@@ -666,20 +655,15 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
   const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OCB);
 
-  // this wave's tiles of step k: tile w*TW + tw, tokens [tb, tb + 16)
-  auto tile_base = [&](int k, int tw) { return t_begin + (int64_t)STEP * k + 16 * (wave * TW + tw); };
-  typedef uint32_t Regs[TW][2][RW];  // Q run, G run of each tile
+  typedef uint32_t Regs[2][RW];  // Q run, G run of this wave's tile
   auto load = [&](int k, Regs& x) {
+    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
+    if (tb + n < t_end) {
+      load_run<D, DT_BF16>(qh + tb * row_bytes + ioff, x[0]);
+      load_run<D, DT_BF16>(gh + tb * row_bytes + ioff, x[1]);
+    } else {
 #pragma unroll
-    for (int tw = 0; tw < TW; ++tw) {
-      const int64_t tb = tile_base(k, tw);
-      if (tb + n < t_end) {
-        load_run<D, DT_BF16>(qh + tb * row_bytes + ioff, x[tw][0]);
-        load_run<D, DT_BF16>(gh + tb * row_bytes + ioff, x[tw][1]);
-      } else {
-#pragma unroll
-        for (int w = 0; w < RW; ++w) { x[tw][0][w] = 0u; x[tw][1][w] = 0u; }
-      }
+      for (int w = 0; w < RW; ++w) { x[0][w] = 0u; x[1][w] = 0u; }
     }
   };
 
@@ -692,130 +676,104 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
   }
 
-  f32x4 ds[RB][NB];  // rows of blocks RB*wave .. RB*wave + RB - 1
+  f32x4 ds[NB];  // rows of block `wave`
 #pragma unroll
-  for (int ii = 0; ii < RB; ++ii)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) ds[ii][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < NB; ++j) ds[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float zacc[Q4];  // dz partial sums per run position over this wave's tokens
 #pragma unroll
   for (int c = 0; c < Q4; ++c) zacc[c] = 0.f;
 
   auto step = [&](int k, const Regs& x) {
-    uint32_t pq[TW][RW];
+    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
+    uint32_t pq[RW];
+    phi_words<DT_BF16, D>(x[0], pq);
+    const uint32_t* pg = x[1];
+    // X = S G (hi + lo) and den = phi(q) . z (z tile) for the tile
+    f32x4 acc[NT], dacc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int tw = 0; tw < TW; ++tw) phi_words<DT_BF16, D>(x[tw][0], pq[tw]);
-    // X = S G (hi + lo; each image read feeds the TW tiles) and den = phi(q) . z
-    f32x4 acc[TW][NT], dacc[TW];
-#pragma unroll
-    for (int tw = 0; tw < TW; ++tw) {
-      dacc[tw] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int i = 0; i < NT; ++i) acc[tw][i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const bf16x8 hi = as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]);
-        const bf16x8 lo = as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]);
-#pragma unroll
-        for (int tw = 0; tw < TW; ++tw) {
-          const uint32_t* pg = x[tw][1];
-          const bf16x8 bt = as_bf16x8(u32x4{pg[4 * s], pg[4 * s + 1], pg[4 * s + 2], pg[4 * s + 3]});
-          acc[tw][i] = mfma_bf16(hi, bt, acc[tw][i]);
-          acc[tw][i] = mfma_bf16(lo, bt, acc[tw][i]);
-        }
+        const bf16x8 bt = as_bf16x8(u32x4{pg[4 * s], pg[4 * s + 1], pg[4 * s + 2], pg[4 * s + 3]});
+        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]), bt, acc[i]);
+        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]), bt, acc[i]);
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const bf16x8 hi = as_bf16x8(zimg[(s * 2 + 0) * 64 + lane]);
-      const bf16x8 lo = as_bf16x8(zimg[(s * 2 + 1) * 64 + lane]);
-#pragma unroll
-      for (int tw = 0; tw < TW; ++tw) {
-        const bf16x8 bt = as_bf16x8(u32x4{pq[tw][4 * s], pq[tw][4 * s + 1], pq[tw][4 * s + 2], pq[tw][4 * s + 3]});
-        dacc[tw] = mfma_bf16(hi, bt, dacc[tw]);
-        dacc[tw] = mfma_bf16(lo, bt, dacc[tw]);
-      }
+      const bf16x8 bt = as_bf16x8(u32x4{pq[4 * s], pq[4 * s + 1], pq[4 * s + 2], pq[4 * s + 3]});
+      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 0) * 64 + lane]), bt, dacc);
+      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 1) * 64 + lane]), bt, dacc);
     }
+    // token-major G of this tile into LDS
 #pragma unroll
-    for (int tw = 0; tw < TW; ++tw) {
-      const int tile = wave * TW + tw;
-      const uint32_t* pg = x[tw][1];
-      // token-major G of this tile into its half of the exchange slots
+    for (int j = 0; j < NB; ++j) {
+      const int s0 = j >> 1;
+      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{pg[4 * s0], pg[4 * s0 + 1], pg[4 * s0 + 2], pg[4 * s0 + 3]}),
+                                 sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
+      ((u32x2*)&xb[wave >> 1][j][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+    }
+    // per token: G . O, dQ, scales
+    float gn = 0.f;
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int s0 = j >> 1;
-        const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{pg[4 * s0], pg[4 * s0 + 1], pg[4 * s0 + 2], pg[4 * s0 + 3]}),
-                                   sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
-        ((u32x2*)&xb[tile >> 1][j][lane])[tile & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
-      }
-      // per token: G . O, dQ, scales
-      float gn = 0.f;
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
+      for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq, 4 * i + r) * acc[i][r];
+    gn = sum_groups(gn);
+    const double rden = 1.0 / (double)dacc[0];
+    const float rd = (float)rden;
+    const float go = gn * rd;
+    const float dd = -go * rd;  // dden; zero for padded tokens (G = 0)
+    const bool ok = tb + n < t_end;
+    char* orow = oh + tb * orow_bytes + ooff;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq[tw], 4 * i + r) * acc[tw][i][r];
-      gn = sum_groups(gn);
-      const double rden = 1.0 / (double)dacc[tw][0];
-      const float rd = (float)rden;
-      const float go = gn * rd;
-      const float dd = -go * rd;  // dden; zero for padded tokens (G = 0)
-      const int64_t tb = tile_base(k, tw);
-      const bool ok = tb + n < t_end;
-      char* orow = oh + tb * orow_bytes + ooff;
+    for (int w = 0; w < NCH; ++w) {
+      uint32_t ow[OCB / 4];
 #pragma unroll
-      for (int w = 0; w < NCH; ++w) {
-        uint32_t ow[OCB / 4];
+      for (int j = 0; j < CH; j += 2) {
+        float o2[2];
 #pragma unroll
-        for (int j = 0; j < CH; j += 2) {
-          float o2[2];
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int c = CH * w + j + u;
-            const float ph = run_val<DT_BF16>(pq[tw], c);
-            o2[u] = (fmaf(-go, zf[RN::feature(g, c)], acc[tw][c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
-          }
-          if constexpr (OT == DT_BF16) {
-            ow[j >> 1] = pack_bf16(o2[0], o2[1]);
-          } else {
-            ow[j] = __float_as_uint(o2[0]);
-            ow[j + 1] = __float_as_uint(o2[1]);
-          }
+        for (int u = 0; u < 2; ++u) {
+          const int c = CH * w + j + u;
+          const float ph = run_val<DT_BF16>(pq, c);
+          o2[u] = (fmaf(-go, zf[RN::feature(g, c)], acc[c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
         }
-        if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
-      }
-      // dz += dden phi(q) (per lane, this lane's token)
-#pragma unroll
-      for (int c = 0; c < Q4; ++c) zacc[c] = fmaf(dd, run_val<DT_BF16>(pq[tw], c), zacc[c]);
-      // token-major phi(q)/den into LDS
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const int s0 = i >> 1;
-        uint32_t wa[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const uint32_t w = pq[tw][4 * s0 + kk];
-          wa[kk] = pack_bf16(bf16lo(w) * rd, bf16hi(w) * rd);
+        if constexpr (OT == DT_BF16) {
+          ow[j >> 1] = pack_bf16(o2[0], o2[1]);
+        } else {
+          ow[j] = __float_as_uint(o2[0]);
+          ow[j + 1] = __float_as_uint(o2[1]);
         }
-        const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
-                                   f32x4{0.f, 0.f, 0.f, 0.f});
-        ((u32x2*)&xa[tile >> 1][i][lane])[tile & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
       }
+      if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
+    }
+    // dz += dden phi(q) (per lane, this lane's token)
+#pragma unroll
+    for (int c = 0; c < Q4; ++c) zacc[c] = fmaf(dd, run_val<DT_BF16>(pq, c), zacc[c]);
+    // token-major phi(q)/den into LDS
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int s0 = i >> 1;
+      uint32_t wa[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t w = pq[4 * s0 + kk];
+        wa[kk] = pack_bf16(bf16lo(w) * rd, bf16hi(w) * rd);
+      }
+      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
+                                 f32x4{0.f, 0.f, 0.f, 0.f});
+      ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     __syncthreads();
-    // this wave's dS row blocks over the step's tiles, one 32-token
-    // contraction per tile pair
+    // dS rows of block `wave` over the eight tiles: tiles (2k, 2k + 1)
+    // make one 32-token contraction
 #pragma unroll
-    for (int kap = 0; kap < KAPS; ++kap) {
+    for (int kap = 0; kap < NW / 2; ++kap) {
+      const bf16x8 aa = as_bf16x8(xa[kap][wave][lane]);
 #pragma unroll
-      for (int ii = 0; ii < RB; ++ii) {
-        const bf16x8 aa = as_bf16x8(xa[kap][RB * wave + ii][lane]);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) ds[ii][j] = mfma_bf16(aa, as_bf16x8(xb[kap][j][lane]), ds[ii][j]);
-      }
+      for (int j = 0; j < NB; ++j) ds[j] = mfma_bf16(aa, as_bf16x8(xb[kap][j][lane]), ds[j]);
     }
     __syncthreads();  // before the next step rewrites xa, xb
   };
@@ -833,10 +791,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   // the workgroup's partial: this wave's row blocks, then dz over all waves
   float* out = part + ((int64_t)bh * P + p) * E;
 #pragma unroll
-  for (int ii = 0; ii < RB; ++ii)
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      *(f32x4*)(out + (((RB * wave + ii) * NB + j) * 64 + lane) * 4) = ds[ii][j];
+  for (int j = 0; j < NB; ++j) *(f32x4*)(out + ((wave * NB + j) * 64 + lane) * 4) = ds[j];
   // dz: each run position summed over the 16 tokens (lanes n) of the group
 #pragma unroll
   for (int c = 0; c < Q4; ++c) {
@@ -848,7 +803,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     if (n == 0) dzs[wave][RN::feature(g, c)] = v;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < D; c += FC::THREADS) {
+  for (int c = threadIdx.x; c < D; c += 512) {
     float v = 0.f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) v += dzs[w][c];
@@ -1003,10 +958,9 @@ static void launch_rows(const BwdArgs& a) {
     // one pass, eight waves sharing each partial
     ProfScope prof("bwd_query_ds", a.stream);
     dim3 fgrid((unsigned)a.P, BH);
-    // eight waves (two per SIMD) with one tile each measured faster than
-    // four waves (one per SIMD) with two tiles each (3.5 vs 4.1 ms)
-    constexpr int NW = 8, TW = 1;
-    bwd_qds4_kernel<OT, NW, TW><<<fgrid, Fused4Cfg<NW, TW>::THREADS, 0, a.stream>>>(
+    // (four waves with two tiles each, one wave per SIMD, measured slower:
+    // 4.1 against 3.5 ms)
+    bwd_qds4_kernel<OT><<<fgrid, 512, 0, a.stream>>>(
         a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
         a.img, a.z64, a.part);
     launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
