@@ -158,6 +158,39 @@ def other_workloads(steps):
         log("%s %.3f ms" % (name, t * 1e3))
         del plan, xs
         torch.cuda.empty_cache()
+
+    # summary reuse: new queries against a cached (S, z) of the long-context
+    # shape (the apply alone: read Q, write O)
+    w = WORKLOAD
+    B, H, N, d = w["B"], w["H"], w["N"], w["d"]
+    xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device="cuda:0") for _ in range(4)]
+    for sid, x in enumerate(xs):
+        la.gen_fill(x, seed=1002, stream_id=sid, std=w["std_qkv"])
+    _, S, z = la.forward(*xs[:3], return_summary=True)
+    t = time_steps(lambda: la.apply(xs[3], S, z, out=xs[0]), max(steps, 20), 3)
+    out["apply_cached_summary_B1_H8_N2097152_d128"] = {
+        "tokens_per_s": round(B * N / t, 1), "ms_per_step": round(t * 1e3, 4),
+        "GB_s": round(2 * B * H * N * d * 2 / t / 1e9, 1)}
+    log("apply with a cached summary %.3f ms" % (t * 1e3))
+    del xs, S, z
+    torch.cuda.empty_cache()
+
+    # the paper's tiles with halos: extract and Hann-weighted blend of a
+    # [T256, 64, 128, C=1024] bf16 field, cores 8 x 16 x 16, halos 2 x 4 x 4
+    dims, core, halo, C = (256, 64, 128), (8, 16, 16), (2, 4, 4), 1024
+    field = torch.empty(dims + (C,), dtype=torch.bfloat16, device="cuda:0")
+    la.gen_fill(field.view(1, 1, -1, C), seed=1003, stream_id=0)
+    tiles = la.tile_extract(field, core, halo)
+    t_ex = time_steps(lambda: la.tile_extract(field, core, halo), max(steps, 10), 2)
+    t_bl = time_steps(lambda: la.tile_blend(tiles, dims, core, halo), max(steps, 10), 2)
+    fb, tb = field.numel() * 2, tiles.numel() * 2
+    out["tiles_T256_Y64_X128_C1024"] = {
+        "core": core, "halo": halo, "tile_bytes": tb, "field_bytes": fb,
+        "extract_ms": round(t_ex * 1e3, 4), "extract_GB_s": round((fb + tb) / t_ex / 1e9, 1),
+        "blend_ms": round(t_bl * 1e3, 4), "blend_GB_s": round((fb + tb) / t_bl / 1e9, 1)}
+    log("tiles: extract %.3f ms, blend %.3f ms" % (t_ex * 1e3, t_bl * 1e3))
+    del field, tiles
+    torch.cuda.empty_cache()
     return out
 
 

@@ -102,9 +102,11 @@ la_status la_version(int32_t* major, int32_t* minor);
  * 1 = backward, 2 = apply), in bytes, 256-byte aligned.  The forward's size depends on
  * (B, H, d, dtype) and on N only through the number of per-tile partial
  * sums, which is capped, so it is bounded independently of N: the state of
- * linear attention per head is O(d^2), whatever the token count.  The
- * backward adds 8 bytes per (b, h, token) for the per-query pair
- * (1/den, dden) passed from its query pass to its dS reduction.
+ * linear attention per head is O(d^2), whatever the token count.  Where
+ * the backward runs its query pass and its dS reduction separately (fp32
+ * inputs, and d = 16) it adds 8 bytes per (b, h, token) for the per-query
+ * pair (1/den, dden) passed between them; bf16 at d >= 32 runs them as one
+ * pass and needs no such buffer.
  */
 la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* bytes);
 

@@ -91,7 +91,10 @@ struct Layout {
 // Forward: [part][S64][z64][img].  Apply: [img].
 // Backward: [img][part][stash][dS64][dz64][dimg]; the stash holds two floats
 // per query token (1/den, -(dO . O)) between the query kernel and the dS
-// reduction, the only part of any workspace that grows with N.
+// reduction, the only part of any workspace that grows with N.  bf16 at
+// d >= 32 fuses the two passes and needs no stash.
+bool fused_backward(const la_attn_desc* d) { return d->in_dtype == LA_BF16 && d->d >= 32; }
+
 Layout layout_for(const la_attn_desc* d, int pass) {
   const int64_t BH = d->B * d->H, D = d->d;
   const Tiling t = choose_tiling(d->N, (int)D);
@@ -111,7 +114,8 @@ Layout layout_for(const la_attn_desc* d, int pass) {
   } else {
     L.img = off; off += img;
     L.part = off; off += part;
-    L.stash = off; off += align_up((size_t)BH * d->N * 2 * sizeof(float));
+    L.stash = off;
+    if (!fused_backward(d)) off += align_up((size_t)BH * d->N * 2 * sizeof(float));
     L.dS64 = off; off += mat;
     L.dz64 = off; off += vec;
     L.dimg = off; off += img;
