@@ -618,7 +618,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   constexpr int RW = D / 8, NCH = RN::NCH, CH = RN::CH;
   constexpr int OES = OT == DT_BF16 ? 2 : 4;
   constexpr int OCB = CH * OES;
-  constexpr int IMG_WORDS = IC::mat_bytes(DT_BF16) / 16;  // the N image
+  constexpr int IMG_WORDS = IC::mat_bytes(DT_BF16) / 32;  // the N image, hi parts
   constexpr int Z_WORDS = IC::tile_bytes(DT_BF16) / 16;   // the T image's z tile
   constexpr int E = D * D + D;
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
@@ -636,7 +636,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   const int64_t b = bh / H, h = bh % H;
   {
     const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT_BF16);
-    stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, false);
+    stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, true);
     stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT_BF16)), Z_WORDS, false);
     for (int c = threadIdx.x; c < D; c += 512) zf[c] = (float)z64[(int64_t)bh * D + c];
   }
@@ -697,8 +697,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const bf16x8 bt = as_bf16x8(u32x4{pg[4 * s], pg[4 * s + 1], pg[4 * s + 2], pg[4 * s + 3]});
-        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 0) * 64 + lane]), bt, acc[i]);
-        acc[i] = mfma_bf16(as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]), bt, acc[i]);
+        acc[i] = mfma_bf16(as_bf16x8(simg[(i * NS + s) * 64 + lane]), bt, acc[i]);
       }
     }
 #pragma unroll
