@@ -11,9 +11,12 @@
 // phi(Q) and phi(K) are recomputed from the inputs here, never stored by
 // the forward (the paper trains with activation recomputation, Sec. III-D).
 //
-// Passes: (1) images of S; (2) query kernel: dQ and per-token (1/den, dden);
-// (3) token reduction for dS, dz (the forward's summary kernel in its
-// backward mode); (4) FP64 combine of dS, dz; (5) key kernel: dK, dV.
+// Passes: (1) images of S; (2) the query pass: dQ and each wave's partial
+// sums of dS, dz in one kernel for bf16 at d >= 32 (bwd_qds_kernel,
+// bwd_qds4_kernel), otherwise the query kernel (dQ and per-token
+// (1/den, dden)) followed by the token reduction for dS, dz (the forward's
+// summary kernel in its backward mode); (3) FP64 combine of dS, dz;
+// (4) key kernel: dK, dV.
 #include <type_traits>
 
 #include "la_kernels.h"
