@@ -314,25 +314,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SummaryCfg<
 }
 
 // ---------------------------------------------------------------------------
-// Combine: FP64 sum of the P per-wave partials in partial order (fixed, so
+// Combine: FP64 sum of the P per-wave partials in a fixed order (so
 // results are bitwise reproducible), writing the dense FP64 matrix M
 // (S or dS) and vector (z or dz), plus the matrix-core operand images.
 // ---------------------------------------------------------------------------
 // Partial layouts: PART_SUMMARY (the summary kernel's tiles: tile (i, j),
 // lane (g, n), register r holds M[F(4g + r) + i][F n + j], F = d/16) and
 // PART_BLOCKS (the fused query backward's: M[16i + 4g + r][16j + n]).
+// Block: 64 elements x 4 quarters of the partials; quarter w sums its
+// partials in order, and the four quarter sums are added as
+// (w0 + w1) + (w2 + w3) -- a fixed order for a given P, so results are
+// bitwise reproducible.
 template <int D, int LAYOUT>
 __global__ __launch_bounds__(256) void combine_kernel(
     const float* __restrict__ part, int P, double* __restrict__ M64,
     double* __restrict__ v64, void* __restrict__ img, int img_dt) {
   constexpr int F = D / 16;
   constexpr int E = D * D + D;
+  __shared__ double qs[4][64];
   const int bh = blockIdx.y;
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u >= E) return;
-  const float* src = part + (int64_t)bh * P * E + u;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += (double)src[(int64_t)p * E];
+  const int e64 = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int u = blockIdx.x * 64 + e64;
+  const int pq = (P + 3) / 4;
+  const int p0 = min(P, w * pq), p1 = min(P, p0 + pq);
+  double sq = 0.0;
+  if (u < E) {
+    const float* src = part + (int64_t)bh * P * E + u;
+    for (int p = p0; p < p1; ++p) sq += (double)src[(int64_t)p * E];
+  }
+  qs[w][e64] = sq;
+  __syncthreads();
+  if (w != 0 || u >= E) return;
+  const double s = (qs[0][e64] + qs[1][e64]) + (qs[2][e64] + qs[3][e64]);
   if (u < D * D) {
     const int r = u & 3, lane = (u >> 2) & 63, ij = u >> 8;
     const int i = ij / F, j = ij % F;
@@ -585,7 +598,7 @@ hipError_t launch_summary(int mode, int dt, int D, const void* k, const void* v,
 template <int D>
 static void launch_combine_d(const float* part, int P, double* M64, double* v64, void* img,
                              int img_dt, int64_t BH, int layout, hipStream_t stream) {
-  dim3 grid((D * D + D + 255) / 256, (unsigned)BH);
+  dim3 grid((D * D + D + 63) / 64, (unsigned)BH);
   if (layout == PART_SUMMARY)
     combine_kernel<D, PART_SUMMARY><<<grid, 256, 0, stream>>>(part, P, M64, v64, img, img_dt);
   else
@@ -614,7 +627,7 @@ static hipError_t launch_forward_d(const FwdArgs& a) {
   launch_summary_d<D>(MODE_FWD, a.in_dt, a.k, a.v, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
                       nullptr, a.part, a.stream);
   {
-    dim3 cgrid((D * D + D + 255) / 256, BH);
+    dim3 cgrid((D * D + D + 63) / 64, BH);
     ProfScope prof("combine", a.stream);
     combine_kernel<D, PART_SUMMARY><<<cgrid, 256, 0, a.stream>>>(a.part, a.P, a.S64, a.z64, a.img,
                                                                  a.in_dt);
