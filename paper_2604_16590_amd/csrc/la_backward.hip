@@ -110,13 +110,15 @@ __device__ __forceinline__ void image_times_runs(
           const bf16x8 lo = as_bf16x8(simg[((i * C::NS + s) * 2 + 1) * 64 + lane]);
 #pragma unroll
           for (int t = 0; t < TT; ++t) {
-            acc[t][i] = mfma_bf16(hi, b[t], acc[t][i]);
+            // the chain's first product starts from zero (no separate clear)
+            acc[t][i] = mfma_bf16(hi, b[t], s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][i]);
             acc[t][i] = mfma_bf16(lo, b[t], acc[t][i]);
           }
         } else {
           const bf16x8 hi = as_bf16x8(simg[(i * C::NS + s) * 64 + lane]);
 #pragma unroll
-          for (int t = 0; t < TT; ++t) acc[t][i] = mfma_bf16(hi, b[t], acc[t][i]);
+          for (int t = 0; t < TT; ++t)
+            acc[t][i] = mfma_bf16(hi, b[t], s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][i]);
         }
       }
       if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
@@ -132,7 +134,8 @@ __device__ __forceinline__ void image_times_runs(
         for (int t4 = 0; t4 < 4; ++t4)
 #pragma unroll
           for (int t = 0; t < TT; ++t)
-            acc[t][i] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]), acc[t][i]);
+            acc[t][i] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]),
+                                 s4 == 0 && t4 == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][i]);
       }
       if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
     }
@@ -156,7 +159,7 @@ __device__ __forceinline__ void tile_times_runs(
 #pragma unroll
       for (int t = 0; t < TT; ++t) {
         const bf16x8 bt = as_bf16x8(u32x4{pw[t][4 * s], pw[t][4 * s + 1], pw[t][4 * s + 2], pw[t][4 * s + 3]});
-        acc[t][0] = mfma_bf16(hi, bt, acc[t][0]);
+        acc[t][0] = mfma_bf16(hi, bt, s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][0]);
         acc[t][0] = mfma_bf16(lo, bt, acc[t][0]);
       }
     }
@@ -169,7 +172,8 @@ __device__ __forceinline__ void tile_times_runs(
       for (int t4 = 0; t4 < 4; ++t4)
 #pragma unroll
         for (int t = 0; t < TT; ++t)
-          acc[t][0] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]), acc[t][0]);
+          acc[t][0] = mfma_f32(__uint_as_float(a[t4]), __uint_as_float(pw[t][4 * s4 + t4]),
+                               s4 == 0 && t4 == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][0]);
     }
   }
 }
@@ -655,19 +659,18 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   const char* qh = (const char*)q + (b * sb + h * sh) * 2;
   const char* gh = (const char*)dout + (b * sb + h * sh) * 2;
   char* oh = (char*)dq + (b * osb + h * osh) * OES;
-  const uint32_t ioff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
   const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OCB);
 
   typedef uint32_t Regs[2][RW];  // Q run, G run of this wave's tile
+  // Rows past the partial's end read its last token again (finite values,
+  // no zero fill); the step gives such tokens a zero scale, so they add
+  // nothing to dS or dz and their dQ rows are not stored.
   auto load = [&](int k, Regs& x) {
-    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
-    if (tb + n < t_end) {
-      load_run<D, DT_BF16>(qh + tb * row_bytes + ioff, x[0]);
-      load_run<D, DT_BF16>(gh + tb * row_bytes + ioff, x[1]);
-    } else {
-#pragma unroll
-      for (int w = 0; w < RW; ++w) { x[0][w] = 0u; x[1][w] = 0u; }
-    }
+    const int64_t tb = min(t_begin + 16 * NW * k + 16 * wave, t_end - 1);  // wave-uniform
+    const int last = (int)min((int64_t)15, t_end - 1 - tb);
+    const uint32_t off = (uint32_t)min(n, last) * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
+    load_run<D, DT_BF16>(qh + tb * row_bytes + off, x[0]);
+    load_run<D, DT_BF16>(gh + tb * row_bytes + off, x[1]);
   };
 
   bf16x8 sel[2];
@@ -700,13 +703,15 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const bf16x8 bt = as_bf16x8(u32x4{pg[4 * s], pg[4 * s + 1], pg[4 * s + 2], pg[4 * s + 3]});
-        acc[i] = mfma_bf16(as_bf16x8(simg[(i * NS + s) * 64 + lane]), bt, acc[i]);
+        acc[i] = mfma_bf16(as_bf16x8(simg[(i * NS + s) * 64 + lane]), bt,
+                           s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[i]);
       }
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const bf16x8 bt = as_bf16x8(u32x4{pq[4 * s], pq[4 * s + 1], pq[4 * s + 2], pq[4 * s + 3]});
-      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 0) * 64 + lane]), bt, dacc);
+      dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 0) * 64 + lane]), bt,
+                       s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : dacc);
       dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 1) * 64 + lane]), bt, dacc);
     }
     // token-major G of this tile into LDS
@@ -724,11 +729,11 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq, 4 * i + r) * acc[i][r];
     gn = sum_groups(gn);
-    const double rden = 1.0 / (double)dacc[0];
-    const float rd = (float)rden;
-    const float go = gn * rd;
-    const float dd = -go * rd;  // dden; zero for padded tokens (G = 0)
     const bool ok = tb + n < t_end;
+    const double rden = 1.0 / (double)dacc[0];
+    const float rd = ok ? (float)rden : 0.f;  // zero past the end: no dS, dz share
+    const float go = gn * rd;
+    const float dd = -go * rd;  // dden
     char* orow = oh + tb * orow_bytes + ooff;
 #pragma unroll
     for (int w = 0; w < NCH; ++w) {
