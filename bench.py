@@ -172,6 +172,16 @@ def other_workloads(steps):
         "tokens_per_s": round(B * N / t, 1), "ms_per_step": round(t * 1e3, 4),
         "GB_s": round(2 * B * H * N * d * 2 / t / 1e9, 1)}
     log("apply with a cached summary %.3f ms" % (t * 1e3))
+    # the noise-gated layer output: spatial attention blended in place into
+    # the temporal branch's output (apply against a cached summary, then the
+    # gated apply: read Q and the other branch, write O)
+    sigma = torch.full((B,), 0.7, dtype=torch.float64, device="cuda:0")
+    t = time_steps(lambda: la.apply_gated(xs[3], S, z, xs[1], sigma, 0.5, out=xs[1]),
+                   max(steps, 20), 3)
+    out["apply_gated_in_place_B1_H8_N2097152_d128"] = {
+        "tokens_per_s": round(B * N / t, 1), "ms_per_step": round(t * 1e3, 4),
+        "GB_s": round(3 * B * H * N * d * 2 / t / 1e9, 1)}
+    log("gated apply in place %.3f ms" % (t * 1e3))
     del xs, S, z
     torch.cuda.empty_cache()
 

@@ -136,6 +136,43 @@ la_status la_apply(const la_attn_desc* desc, const void* q, const double* s,
                    const double* z, void* o, void* ws, size_t ws_bytes, la_stream stream);
 
 /*
+ * Noise-gated mixing of two attention branches (Sec. III-B: each denoiser
+ * layer weighs its spatial self-attention against its temporal
+ * cross-attention by the diffusion noise level, leaning on the temporal
+ * branch when the noise is high and on the spatial one when it is low).
+ * The paper does not give the gate; this library reads it as a logistic
+ * function of log noise centred on the EDM data scale sigma_data (the
+ * paper's diffusion follows Karras et al., Sec. III-A):
+ *     g_b   = sigma_data / (sigma_data + sigma[b])
+ *           = 1 / (1 + exp(ln sigma[b] - ln sigma_data))     spatial weight
+ *     out_i = g_b * A_i + (1 - g_b) * other_i
+ * where A is the attention these calls compute (la_forward_gated: of
+ * q, k, v; la_apply_gated: of q against a given S, z) and other is the
+ * other branch's stored output.  g_b is 1 at sigma = 0 (out = A), 1/2 at
+ * sigma = sigma_data and 0 at sigma = +inf (out = other).  The blend is
+ * fused into the attention's output pass: other is read once, A is never
+ * stored, and the cost over la_forward / la_apply is one more read of a
+ * tensor of o's size.
+ *
+ * other: device, out_dtype with the out strides (the layout of o); it may
+ * be o itself (in place), and must not otherwise overlap o.  sigma: device,
+ * B FP64 noise levels, each >= 0 (+inf allowed); other values give
+ * unspecified weights (never a fault).  sigma_data: host, finite, > 0
+ * (EDM uses 0.5).  The remaining arguments and the workspace (pass 0 for
+ * la_forward_gated, 2 for la_apply_gated) are those of la_forward and
+ * la_apply.  Errors: LA_ERR_INVALID_ARG for a NULL or misaligned other or
+ * sigma (16 and 8 bytes) or a bad sigma_data, then as la_forward/la_apply.
+ */
+la_status la_forward_gated(const la_attn_desc* desc, const void* q, const void* k,
+                           const void* v, const void* other, const double* sigma,
+                           double sigma_data, void* o, double* s_out, double* z_out,
+                           void* ws, size_t ws_bytes, la_stream stream);
+la_status la_apply_gated(const la_attn_desc* desc, const void* q, const double* s,
+                         const double* z, const void* other, const double* sigma,
+                         double sigma_data, void* o, void* ws, size_t ws_bytes,
+                         la_stream stream);
+
+/*
  * Backward pass of L = <O, dO>: writes (does not accumulate) dq, dk, dv in
  * out_dtype with the out strides.  s and z are the forward's s_out and
  * z_out for the same q, k, v.  phi(Q) and phi(K) are recomputed from the

@@ -83,6 +83,9 @@ def _load(path=None):
         lib.oracle_tile_blend.argtypes = [i64p, i64p, i64p, i64, dp, dp]
         lib.oracle_hann.restype = ctypes.c_double
         lib.oracle_hann.argtypes = [i64, i64]
+        lib.oracle_noise_gate.restype = ctypes.c_double
+        lib.oracle_noise_gate.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_gated_mix.argtypes = [i64, i64, i64, i64, dp, T, dp, ctypes.c_double, dp]
         _lib = lib
     return _lib
 
@@ -241,3 +244,22 @@ def tile_blend(tiles, dims, core, halo):
 
 def hann(u, L):
     return _load().oracle_hann(int(u), int(L))
+
+
+def noise_gate(sigma: float, sigma_data: float = 0.5) -> float:
+    """Spatial weight g(sigma) = sigma_data / (sigma_data + sigma)."""
+    return _load().oracle_noise_gate(float(sigma), float(sigma_data))
+
+
+def gated_mix(a, other, sigma, sigma_data=0.5):
+    """g(sigma_b) * a + (1 - g(sigma_b)) * other per batch element (FP64)."""
+    a = np.ascontiguousarray(a, np.float64)
+    B, H, N, d = a.shape
+    assert other.shape == a.shape
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, np.float64), (B,)))
+    out = np.empty_like(a)
+    rc = _load().oracle_gated_mix(B, H, N, d, _dptr(a), _tensor(other), _dptr(sig),
+                                  float(sigma_data), _dptr(out))
+    if rc:
+        raise ValueError("oracle_gated_mix rejected its arguments")
+    return out

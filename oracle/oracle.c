@@ -373,3 +373,27 @@ int oracle_tile_blend(const int64_t* dims, const int64_t* core, const int64_t* h
   free(wsum);
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Noise-gated mixing (Sec. III-B).  The spatial weight is the logistic
+ * function of -(ln sigma - ln sigma_data), written as the ratio it equals;
+ * sigma = 0 gives 1 and sigma = +inf gives 0.
+ * ---------------------------------------------------------------------- */
+double oracle_noise_gate(double sigma, double sigma_data) {
+  return sigma_data / (sigma_data + sigma);
+}
+
+int oracle_gated_mix(int64_t B, int64_t H, int64_t N, int64_t d, const double* a,
+                     oracle_tensor other, const double* sigma, double sigma_data, double* out) {
+  if (B < 1 || H < 1 || N < 0 || d < 1 || !a || !sigma || !out || !(sigma_data > 0.0)) return -1;
+  for (int64_t b = 0; b < B; ++b) {
+    const double g = oracle_noise_gate(sigma[b], sigma_data);
+    for (int64_t h = 0; h < H; ++h)
+      for (int64_t n = 0; n < N; ++n)
+        for (int64_t c = 0; c < d; ++c) {
+          const int64_t i = ((b * H + h) * N + n) * d + c;
+          out[i] = g * a[i] + (1.0 - g) * elem(&other, b, h, n, c);
+        }
+  }
+  return 0;
+}

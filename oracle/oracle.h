@@ -105,6 +105,24 @@ int oracle_tile_blend(const int64_t* dims, const int64_t* core, const int64_t* h
                       int64_t C, const double* tiles, double* out);
 double oracle_hann(int64_t u, int64_t L);
 
+/*
+ * Noise-gated mixing of two attention branches (Sec. III-B: the denoiser
+ * weighs spatial self-attention against temporal cross-attention by the
+ * diffusion noise level sigma, more temporal at high noise, more spatial at
+ * low noise).  The paper gives no formula; the reading adopted is a
+ * logistic function of log noise centred on the EDM data scale sigma_data
+ * (the diffusion follows Karras et al., Sec. III-A):
+ *   g(sigma) = 1 / (1 + exp(ln sigma - ln sigma_data))
+ *            = sigma_data / (sigma_data + sigma)        (spatial weight)
+ *   out     = g(sigma_b) * A + (1 - g(sigma_b)) * other  per batch element b
+ * oracle_gated_mix: a is dense FP64 [B][H][N][d] (this branch's attention,
+ * e.g. from oracle_forward), other is read like an input (its stored
+ * dtype and strides), sigma has B entries; out is dense FP64.
+ */
+double oracle_noise_gate(double sigma, double sigma_data);
+int oracle_gated_mix(int64_t B, int64_t H, int64_t N, int64_t d, const double* a,
+                     oracle_tensor other, const double* sigma, double sigma_data, double* out);
+
 /* Number of OpenMP threads the oracle will use. */
 int oracle_threads(void);
 

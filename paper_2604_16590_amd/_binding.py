@@ -70,7 +70,12 @@ def lib():
         L.la_forward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
         L.la_backward.argtypes = [DP, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
         L.la_apply.argtypes = [DP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
-        for name in ("la_version", "la_workspace_size", "la_forward", "la_backward", "la_apply"):
+        L.la_forward_gated.argtypes = [DP, VP, VP, VP, VP, VP, ctypes.c_double, VP, VP, VP, VP,
+                                       ctypes.c_size_t, VP]
+        L.la_apply_gated.argtypes = [DP, VP, VP, VP, VP, VP, ctypes.c_double, VP, VP,
+                                     ctypes.c_size_t, VP]
+        for name in ("la_version", "la_workspace_size", "la_forward", "la_backward", "la_apply",
+                     "la_forward_gated", "la_apply_gated"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -181,6 +186,69 @@ def apply(q, S, z, out_dtype=None, out=None):
     ws = _workspace(workspace_size(desc, 2), q.device)
     _check("la_apply", lib().la_apply(ctypes.byref(desc), q.data_ptr(), S.data_ptr(), z.data_ptr(),
                                       out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return out
+
+
+def _gate_args(q, other, out, sigma):
+    """Checks the other branch's output against out; sigma as a [B] float64
+    device tensor (a Python number is one level for every batch element)."""
+    if other.shape != out.shape or other.dtype != out.dtype or other.device != out.device:
+        raise ValueError("other must match the output in shape, dtype and device")
+    if _strides(other) != _strides(out):
+        raise ValueError("other must have the output's strides")
+    B = q.shape[0]
+    if not torch.is_tensor(sigma):
+        sigma = torch.full((B,), float(sigma), dtype=torch.float64, device=q.device)
+    if sigma.shape != (B,) or sigma.dtype != torch.float64 or sigma.device != q.device:
+        raise ValueError("sigma must be a [B] float64 tensor on q's device")
+    return sigma.contiguous()
+
+
+def forward_gated(q, k, v, other, sigma, sigma_data=0.5, out=None, return_summary=False):
+    """Noise-gated blend g*A + (1 - g)*other of this attention A with another
+    branch's output, g = sigma_data / (sigma_data + sigma[b]) per batch
+    element; `other` may be `out` (in place)."""
+    _same_layout(q, k, "k")
+    _same_layout(q, v, "v")
+    if not q.is_cuda:
+        raise ValueError("inputs must be GPU tensors")
+    B, H, N, d = q.shape
+    if out is None:
+        out = torch.empty((B, H, N, d), dtype=other.dtype, device=q.device)
+    sigma = _gate_args(q, other, out, sigma)
+    desc = make_desc(q, out)
+    ws = _workspace(workspace_size(desc, 0), q.device)
+    S = z = None
+    if return_summary:
+        S = torch.empty((B, H, d, d), dtype=torch.float64, device=q.device)
+        z = torch.empty((B, H, d), dtype=torch.float64, device=q.device)
+    _check("la_forward_gated", lib().la_forward_gated(
+        ctypes.byref(desc), q.data_ptr(), k.data_ptr(), v.data_ptr(), other.data_ptr(),
+        sigma.data_ptr(), float(sigma_data), out.data_ptr(),
+        S.data_ptr() if S is not None else None, z.data_ptr() if z is not None else None,
+        ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return (out, S, z) if return_summary else out
+
+
+def apply_gated(q, S, z, other, sigma, sigma_data=0.5, out=None):
+    """apply() blended with another branch's output as in forward_gated()."""
+    if not q.is_cuda:
+        raise ValueError("inputs must be GPU tensors")
+    B, H, N, d = q.shape
+    if S.shape != (B, H, d, d) or z.shape != (B, H, d) or S.dtype != torch.float64 \
+            or z.dtype != torch.float64:
+        raise ValueError("S must be [B,H,d,d] and z [B,H,d], float64")
+    S = S.contiguous()
+    z = z.contiguous()
+    if out is None:
+        out = torch.empty((B, H, N, d), dtype=other.dtype, device=q.device)
+    sigma = _gate_args(q, other, out, sigma)
+    desc = make_desc(q, out)
+    ws = _workspace(workspace_size(desc, 2), q.device)
+    _check("la_apply_gated", lib().la_apply_gated(
+        ctypes.byref(desc), q.data_ptr(), S.data_ptr(), z.data_ptr(), other.data_ptr(),
+        sigma.data_ptr(), float(sigma_data), out.data_ptr(), ws.data_ptr(), ws.numel(),
+        _stream(q.device)))
     return out
 
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 
@@ -124,6 +125,75 @@ Layout layout_for(const la_attn_desc* d, int pass) {
   return L;
 }
 
+// The gate's arguments (the attention's own are checked by the caller).
+la_status check_gate(const void* other, const double* sigma, double sigma_data) {
+  if (!other || !sigma) return LA_ERR_INVALID_ARG;
+  if (!aligned16(other) || ((uintptr_t)sigma & 7u)) return LA_ERR_INVALID_ARG;
+  if (!(sigma_data > 0.0) || !std::isfinite(sigma_data)) return LA_ERR_INVALID_ARG;
+  return LA_OK;
+}
+
+la_status forward_impl(const la_attn_desc* desc, const void* q, const void* k, const void* v,
+                       void* o, double* s_out, double* z_out, void* ws, size_t ws_bytes,
+                       la_stream stream, const void* other, const double* sigma,
+                       double sigma_data) {
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  if (!q || !k || !v || !o || !ws) return LA_ERR_INVALID_ARG;
+  if (!aligned16(q) || !aligned16(k) || !aligned16(v) || !aligned16(o)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)s_out & 7u) || ((uintptr_t)z_out & 7u)) return LA_ERR_INVALID_ARG;
+  const Layout L = layout_for(desc, 0);
+  if (ws_bytes < L.total) return LA_ERR_OOM;
+  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  char* w = (char*)ws;
+  la::FwdArgs a{};
+  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
+  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
+  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
+  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
+  a.q = q; a.k = k; a.v = v; a.o = o;
+  a.P = t.P; a.Tw = t.Tw; a.Ta = t.Ta;
+  a.part = (float*)(w + L.part);
+  a.S64 = s_out ? s_out : (double*)(w + L.S64);
+  a.z64 = z_out ? z_out : (double*)(w + L.z64);
+  a.img = w + L.img;
+  a.other = other; a.sigma = sigma; a.sigma_data = sigma_data;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = la::launch_forward(a);
+  if (e != hipSuccess) return hip_fail(e);
+  return LA_OK;
+}
+
+la_status apply_impl(const la_attn_desc* desc, const void* q, const double* s, const double* z,
+                     void* o, void* ws, size_t ws_bytes, la_stream stream, const void* other,
+                     const double* sigma, double sigma_data) {
+  la_status st = check_desc(desc);
+  if (st != LA_OK) return st;
+  if (!q || !s || !z || !o || !ws) return LA_ERR_INVALID_ARG;
+  if (!aligned16(q) || !aligned16(o)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)s & 7u) || ((uintptr_t)z & 7u)) return LA_ERR_INVALID_ARG;
+  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
+  const Layout L = layout_for(desc, 2);
+  if (ws_bytes < L.total) return LA_ERR_OOM;
+  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  la::FwdArgs a{};
+  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
+  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
+  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
+  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
+  a.q = q; a.o = o;
+  a.Ta = t.Ta;
+  a.S64 = const_cast<double*>(s);
+  a.z64 = const_cast<double*>(z);
+  a.img = (char*)ws + L.img;
+  a.other = other; a.sigma = sigma; a.sigma_data = sigma_data;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = la::launch_apply(a);
+  if (e != hipSuccess) return hip_fail(e);
+  return LA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -162,58 +232,31 @@ la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* byte
 la_status la_forward(const la_attn_desc* desc, const void* q, const void* k,
                      const void* v, void* o, double* s_out, double* z_out,
                      void* ws, size_t ws_bytes, la_stream stream) {
-  la_status st = check_desc(desc);
+  return forward_impl(desc, q, k, v, o, s_out, z_out, ws, ws_bytes, stream, nullptr, nullptr, 0.0);
+}
+
+la_status la_forward_gated(const la_attn_desc* desc, const void* q, const void* k,
+                           const void* v, const void* other, const double* sigma,
+                           double sigma_data, void* o, double* s_out, double* z_out,
+                           void* ws, size_t ws_bytes, la_stream stream) {
+  const la_status st = check_gate(other, sigma, sigma_data);
   if (st != LA_OK) return st;
-  if (!q || !k || !v || !o || !ws) return LA_ERR_INVALID_ARG;
-  if (!aligned16(q) || !aligned16(k) || !aligned16(v) || !aligned16(o)) return LA_ERR_INVALID_ARG;
-  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
-  if (((uintptr_t)s_out & 7u) || ((uintptr_t)z_out & 7u)) return LA_ERR_INVALID_ARG;
-  const Layout L = layout_for(desc, 0);
-  if (ws_bytes < L.total) return LA_ERR_OOM;
-  const Tiling t = choose_tiling(desc->N, (int)desc->d);
-  char* w = (char*)ws;
-  la::FwdArgs a{};
-  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
-  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
-  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
-  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
-  a.q = q; a.k = k; a.v = v; a.o = o;
-  a.P = t.P; a.Tw = t.Tw; a.Ta = t.Ta;
-  a.part = (float*)(w + L.part);
-  a.S64 = s_out ? s_out : (double*)(w + L.S64);
-  a.z64 = z_out ? z_out : (double*)(w + L.z64);
-  a.img = w + L.img;
-  a.stream = (hipStream_t)stream;
-  hipError_t e = la::launch_forward(a);
-  if (e != hipSuccess) return hip_fail(e);
-  return LA_OK;
+  return forward_impl(desc, q, k, v, o, s_out, z_out, ws, ws_bytes, stream, other, sigma,
+                      sigma_data);
 }
 
 la_status la_apply(const la_attn_desc* desc, const void* q, const double* s,
                    const double* z, void* o, void* ws, size_t ws_bytes, la_stream stream) {
-  la_status st = check_desc(desc);
+  return apply_impl(desc, q, s, z, o, ws, ws_bytes, stream, nullptr, nullptr, 0.0);
+}
+
+la_status la_apply_gated(const la_attn_desc* desc, const void* q, const double* s,
+                         const double* z, const void* other, const double* sigma,
+                         double sigma_data, void* o, void* ws, size_t ws_bytes,
+                         la_stream stream) {
+  const la_status st = check_gate(other, sigma, sigma_data);
   if (st != LA_OK) return st;
-  if (!q || !s || !z || !o || !ws) return LA_ERR_INVALID_ARG;
-  if (!aligned16(q) || !aligned16(o)) return LA_ERR_INVALID_ARG;
-  if (((uintptr_t)s & 7u) || ((uintptr_t)z & 7u)) return LA_ERR_INVALID_ARG;
-  if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
-  const Layout L = layout_for(desc, 2);
-  if (ws_bytes < L.total) return LA_ERR_OOM;
-  const Tiling t = choose_tiling(desc->N, (int)desc->d);
-  la::FwdArgs a{};
-  a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
-  a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
-  a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
-  a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
-  a.q = q; a.o = o;
-  a.Ta = t.Ta;
-  a.S64 = const_cast<double*>(s);
-  a.z64 = const_cast<double*>(z);
-  a.img = (char*)ws + L.img;
-  a.stream = (hipStream_t)stream;
-  hipError_t e = la::launch_apply(a);
-  if (e != hipSuccess) return hip_fail(e);
-  return LA_OK;
+  return apply_impl(desc, q, s, z, o, ws, ws_bytes, stream, other, sigma, sigma_data);
 }
 
 la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,

@@ -395,11 +395,20 @@ struct ApplyCfg {
   static constexpr int QW = QB / 4;
 };
 
-template <int DT, int OT, int D>
+//
+// MIX: the noise-gated epilogue.  Batch element b's spatial weight
+// g_b = sigma_data / (sigma_data + sigma[b]) (FP64, once per workgroup)
+// blends this attention with another branch's stored output (same dtype
+// and strides as o): o = g_b A + (1 - g_b) other, in FP32 before the
+// store.  The other branch's rows travel in the same register sets as the
+// queries, a step ahead, where registers allow (bf16 in and out).  `other`
+// may be `o` itself: each lane reads its elements before it writes them.
+template <int DT, int OT, int D, bool MIX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void apply_kernel(
     const void* __restrict__ q, int64_t sb, int64_t sh, int64_t sn,
-    void* __restrict__ o, int64_t osb, int64_t osh, int64_t osn, int H,
-    int64_t N, int Ta, const void* __restrict__ img) {
+    void* o, int64_t osb, int64_t osh, int64_t osn, int H,
+    int64_t N, int Ta, const void* __restrict__ img, const void* other,
+    const double* __restrict__ sigma, double sigma_data) {
   using IC = ImageCfg<D>;
   using AC = ApplyCfg<DT, D>;
   constexpr int Q4 = D / 4;
@@ -433,25 +442,62 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const uint32_t qoff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
   const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * RN::CH * OES);
 
-  typedef uint32_t QRegs[TT][QW];
-  auto load_q = [&](int64_t t0, QRegs& qw) {
+  // the gate: spatial weight gw, the other branch's weight hw
+  float gw = 1.f, hw = 0.f;
+  const char* xh = nullptr;
+  if constexpr (MIX) {
+    const double gg = sigma_data / (sigma_data + sigma[b]);
+    gw = (float)gg;
+    hw = (float)(1.0 - gg);
+    xh = (const char*)other + (b * osb + h * osh) * OES;
+  }
+  constexpr int XW = MIX ? Q4 * OES / 4 : 1;  // words of a lane's run of `other`
+  // bf16 in and out: `other` rides in the query register sets, a step
+  // ahead; otherwise (registers) it is loaded as its step starts
+  constexpr bool XPF = MIX && DT == DT_BF16 && OT == DT_BF16;
+
+  struct QRegs {
+    uint32_t q[TT][QW];
+    uint32_t x[TT][XPF ? XW : 1];
+  };
+  auto load_x = [&](int64_t tb, uint32_t* xw) {
+    load_out_run<D, DT, OT>(xh + tb * orow_bytes + ooff, xw);
+  };
+  auto load_one = [&](int tt, int64_t tb, QRegs& r) {
+    load_run<D, DT>(qh + tb * row_bytes + qoff, r.q[tt]);
+    if constexpr (XPF) load_x(tb, r.x[tt]);
+  };
+  auto load_q = [&](int64_t t0, QRegs& r) {
     if (t0 + 16 * TT <= wg_end) {
 #pragma unroll
-      for (int tt = 0; tt < TT; ++tt) load_run<D, DT>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+      for (int tt = 0; tt < TT; ++tt) load_one(tt, t0 + 16 * tt, r);
     } else {
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
         if (t0 + 16 * tt + n < wg_end) {
-          load_run<D, DT>(qh + (t0 + 16 * tt) * row_bytes + qoff, qw[tt]);
+          load_one(tt, t0 + 16 * tt, r);
         } else {
 #pragma unroll
-          for (int w = 0; w < QW; ++w) qw[tt][w] = 0;
+          for (int w = 0; w < QW; ++w) r.q[tt][w] = 0;
+          if constexpr (XPF) {
+#pragma unroll
+            for (int w = 0; w < XW; ++w) r.x[tt][w] = 0;
+          }
         }
       }
     }
   };
 
-  auto compute = [&](int64_t t0, const QRegs& qw) {
+  auto compute = [&](int64_t t0, const QRegs& r) {
+    const auto& qw = r.q;
+    // `other` when not prefetched: loaded as the step starts (bf16 queries)
+    // or just before its use (fp32 queries, whose runs fill the registers)
+    uint32_t xs[TT][MIX && !XPF ? XW : 1];
+    if constexpr (MIX && !XPF && DT == DT_BF16) {
+#pragma unroll
+      for (int tt = 0; tt < TT; ++tt)
+        if (t0 + 16 * tt + n < wg_end) load_x(t0 + 16 * tt, xs[tt]);
+    }
     // phi(q) as matrix-core operands; acc[tt][NT] is the z tile (den)
     f32x4 acc[TT][NT + 1];
 #pragma unroll
@@ -487,7 +533,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
           const bf16x8 lo = as_bf16x8(simg[((i * NS + s) * 2 + 1) * 64 + lane]);
 #pragma unroll
           for (int tt = 0; tt < TT; ++tt) {
-            acc[tt][i] = mfma_bf16(hi, bq[tt][s], acc[tt][i]);
+            // the chain's first product starts from zero (no separate clear)
+            acc[tt][i] = mfma_bf16(hi, bq[tt][s], s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[tt][i]);
             acc[tt][i] = mfma_bf16(lo, bq[tt][s], acc[tt][i]);
           }
           // keep the operand reads next to their use (bounded registers)
@@ -508,7 +555,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
           for (int t4 = 0; t4 < 4; ++t4)
 #pragma unroll
             for (int tt = 0; tt < TT; ++tt)
-              acc[tt][i] = mfma_f32(__uint_as_float(a[t4]), pq[tt][4 * s4 + t4], acc[tt][i]);
+              acc[tt][i] = mfma_f32(__uint_as_float(a[t4]), pq[tt][4 * s4 + t4],
+                                    s4 == 0 && t4 == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[tt][i]);
           if constexpr (D >= 128) __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -526,6 +574,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             out[4 * i + r] = fmaf(acc[tt][i][r], rh, acc[tt][i][r] * rl);
+        if constexpr (MIX) {
+          if constexpr (!XPF && DT != DT_BF16) load_x(t0 + 16 * tt, xs[tt]);
+#pragma unroll
+          for (int c = 0; c < Q4; ++c)
+            out[c] = fmaf(gw, out[c], hw * word_elem<OT>(XPF ? r.x[tt] : xs[tt], c));
+        }
         store_run<D, DT, OT>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
       }
     }
@@ -639,14 +693,22 @@ template <int D>
 static hipError_t launch_apply_only(const FwdArgs& a) {
   const int BH = (int)(a.B * a.H);
   dim3 agrid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
-  ProfScope prof("apply", a.stream);
-#define LA_APPLY(DTI, DTO)                                                       \
-  apply_kernel<DTI, DTO, D><<<agrid, 256, 0, a.stream>>>(                         \
-      a.q, a.sb, a.sh, a.sn, a.o, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img)
-  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) LA_APPLY(DT_BF16, DT_BF16);
-  else if (a.in_dt == DT_BF16) LA_APPLY(DT_BF16, DT_FP32);
-  else if (a.out_dt == DT_BF16) LA_APPLY(DT_FP32, DT_BF16);
-  else LA_APPLY(DT_FP32, DT_FP32);
+  ProfScope prof(a.other ? "apply_gated" : "apply", a.stream);
+#define LA_APPLY(DTI, DTO, MIX)                                                   \
+  apply_kernel<DTI, DTO, D, MIX><<<agrid, 256, 0, a.stream>>>(                     \
+      a.q, a.sb, a.sh, a.sn, a.o, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img, a.other, \
+      a.sigma, a.sigma_data)
+#define LA_APPLY_DT(MIX)                                                \
+  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) LA_APPLY(DT_BF16, DT_BF16, MIX); \
+  else if (a.in_dt == DT_BF16) LA_APPLY(DT_BF16, DT_FP32, MIX);                   \
+  else if (a.out_dt == DT_BF16) LA_APPLY(DT_FP32, DT_BF16, MIX);                  \
+  else LA_APPLY(DT_FP32, DT_FP32, MIX);
+  if (a.other) {
+    LA_APPLY_DT(true)
+  } else {
+    LA_APPLY_DT(false)
+  }
+#undef LA_APPLY_DT
 #undef LA_APPLY
   return hipGetLastError();
 }

@@ -59,6 +59,19 @@ __device__ __forceinline__ void store_run(char* p, const float* x) {
   }
 }
 
+// Load a lane's run of stored output values (type OT, the layout store_run
+// writes; p = row start + CH * sizeof(OT) * g) as words; element c of the
+// run is word_elem<OT>(w, c).
+template <int D, int DT, int OT>
+__device__ __forceinline__ void load_out_run(const char* p, uint32_t* w) {
+  using R = Run<D, DT>;
+  constexpr int OES = OT == DT_BF16 ? 2 : 4;
+  constexpr int OCB = R::CH * OES;
+  constexpr int OW = OCB / 4;
+#pragma unroll
+  for (int c = 0; c < R::NCH; ++c) load_words<OCB>(p + c * 4 * OCB, w + c * OW);
+}
+
 // Matrix-core operand images of a d x d matrix M (S or dS), per head:
 //   T image: A[row = value feature e][k = key/query feature c] = M[c][e],
 //            followed by a z tile: A[row = any of 16][k = c] = v[c] (the
@@ -177,6 +190,11 @@ struct FwdArgs {
   double* S64;         // [BH][D][D]
   double* z64;         // [BH][D]
   void* img;           // [BH][2 images]
+  // noise-gated mix (null `other`: plain output): o = g_b A + (1 - g_b) other,
+  // g_b = sigma_data / (sigma_data + sigma[b])
+  const void* other;   // output dtype and strides
+  const double* sigma; // [B]
+  double sigma_data;
   hipStream_t stream;
 };
 

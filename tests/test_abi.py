@@ -98,6 +98,34 @@ def test_forward_rejects_bad_pointers_before_gpu_work():
     assert L.la_apply(ctypes.byref(d), fake, fake, fake, fake, fake, ws.value - 1, None) == 3
 
 
+def test_gated_calls_reject_bad_gate_arguments_before_gpu_work():
+    L = la.lib()
+    d = desc()
+    ws0, ws2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    L.la_workspace_size(ctypes.byref(d), 0, ctypes.byref(ws0))
+    L.la_workspace_size(ctypes.byref(d), 2, ctypes.byref(ws2))
+    fake = 1 << 20  # never dereferenced: every case fails validation first
+    qkv = [fake, fake, fake]
+    for other, sigma, sd, status in ((None, fake, 0.5, 1), (fake + 8, fake, 0.5, 1),
+                                     (fake, None, 0.5, 1), (fake, fake + 4, 0.5, 1),
+                                     (fake, fake, 0.0, 1), (fake, fake, -1.0, 1),
+                                     (fake, fake, float("nan"), 1), (fake, fake, float("inf"), 1)):
+        assert L.la_forward_gated(ctypes.byref(d), *qkv, other, sigma, sd, fake, None, None, fake,
+                                  ws0.value, None) == status
+        assert L.la_apply_gated(ctypes.byref(d), fake, fake, fake, other, sigma, sd, fake, fake,
+                                ws2.value, None) == status
+    # good gate, then the attention's own checks
+    assert L.la_forward_gated(ctypes.byref(d), None, fake, fake, fake, fake, 0.5, fake, None, None,
+                              fake, ws0.value, None) == 1
+    assert L.la_forward_gated(ctypes.byref(d), *qkv, fake, fake, 0.5, fake, None, None, fake,
+                              ws0.value - 1, None) == 3
+    assert L.la_apply_gated(ctypes.byref(d), fake, fake, fake, fake, fake, 0.5, fake, fake,
+                            ws2.value - 1, None) == 3
+    bad = desc(N=0)
+    assert L.la_apply_gated(ctypes.byref(bad), fake, fake, fake, fake, fake, 0.5, fake, fake,
+                            ws2.value, None) == 1
+
+
 def test_generator_rejects_bad_arguments():
     G = B.gen_lib()
     spec = B.GenSpec(1, 0, 0, 0.0, 1.0, 0, 0, 0, 1.0, 0)

@@ -264,3 +264,62 @@ def test_constant_values_have_zero_query_and_key_gradients():
     v = np.broadcast_to(rnd((1, 1, 1, 16), 60), q.shape).copy()
     dq, dk, _ = oracle.backward(q, k, v, g)
     assert np.abs(dq).max() < 1e-14 and np.abs(dk).max() < 1e-14
+
+
+# -- noise-gated mixing (Sec. III-B; the gate's form is a stated reading) ----
+
+def test_noise_gate_is_the_logistic_of_log_noise():
+    """g(sigma) equals scipy's logistic function of ln(sigma_data / sigma)."""
+    special = pytest.importorskip("scipy.special")
+    for sd in (0.5, 1.0, 0.03):
+        for sigma in (1e-4, 0.002, 0.1, 0.5, 1.0, 7.0, 80.0, 1e3):
+            ref = special.expit(math.log(sd) - math.log(sigma))
+            assert abs(oracle.noise_gate(sigma, sd) - ref) <= 4e-16 * max(1.0, ref)
+
+
+def test_noise_gate_special_values_and_direction():
+    assert oracle.noise_gate(0.0, 0.5) == 1.0          # no noise: spatial only
+    assert oracle.noise_gate(math.inf, 0.5) == 0.0     # pure noise: temporal only
+    assert oracle.noise_gate(0.5, 0.5) == 0.5          # the data scale is the midpoint
+    sig = [0.002, 0.01, 0.1, 0.5, 2.0, 10.0, 80.0]
+    g = [oracle.noise_gate(s, 0.5) for s in sig]
+    assert all(a > b for a, b in zip(g, g[1:])), "more noise must weigh the temporal branch more"
+    # reflection about the data scale: g(sd^2 / s) = 1 - g(s)
+    for s in sig:
+        assert abs(oracle.noise_gate(0.25 / s, 0.5) - (1.0 - oracle.noise_gate(s, 0.5))) < 1e-15
+
+
+def test_gated_mix_of_quadratic_forms():
+    """The blend of a brute-force spatial attention with another branch,
+    per batch element, checked at the gate's fixed points and in between."""
+    B, H, N, d = 4, 2, 60, 8
+    q, k, v = (rnd((B, H, N, d), s) for s in (61, 62, 63))
+    other = rnd((B, H, N, d), 64).astype(np.float32)
+    sigma = np.array([0.0, 0.5, 3.0, math.inf])
+    a = quadratic_form(q, k, v)
+    out = oracle.gated_mix(oracle.forward(q, k, v), other, sigma, 0.5)
+    np.testing.assert_allclose(out[0], a[0], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(out[1], 0.5 * (a[1] + other[1].astype(np.float64)), rtol=1e-12, atol=1e-13)
+    w = 0.5 / 3.5
+    np.testing.assert_allclose(out[2], w * a[2] + (1 - w) * other[2].astype(np.float64), rtol=1e-12,
+                               atol=1e-13)
+    assert np.array_equal(out[3], other[3].astype(np.float64))
+    # a convex combination: every element lies between the two branches
+    lo, hi = np.minimum(a, other), np.maximum(a, other)
+    assert np.all(out >= lo - 1e-12) and np.all(out <= hi + 1e-12)
+
+
+def test_gated_mix_reads_other_like_an_input():
+    """bf16 bit patterns and strided views are read exactly."""
+    B, H, N, d = 2, 2, 9, 4
+    a = rnd((B, H, N, d), 65)
+    vals = rnd((B, H, N, d), 66).astype(np.float32)
+    bits = (vals.view(np.uint32) >> 16).astype(np.uint16)
+    exact = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    out = oracle.gated_mix(a, bits, [1.0, 2.0], 1.0)
+    g = np.array([0.5, 1.0 / 3.0]).reshape(B, 1, 1, 1)
+    np.testing.assert_allclose(out, g * a + (1 - g) * exact, rtol=1e-15, atol=1e-15)
+    wide = np.zeros((B, N, H, d), np.float32)
+    wide[...] = vals.transpose(0, 2, 1, 3)
+    view = wide.transpose(0, 2, 1, 3)  # BNHD storage seen as [B, H, N, d]
+    np.testing.assert_array_equal(oracle.gated_mix(a, view, 0.3), oracle.gated_mix(a, vals, 0.3))

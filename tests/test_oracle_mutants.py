@@ -34,6 +34,17 @@ MUTANTS = {
                              "dS[c * d + e] += p * elem(g, b, h, i, e);"),
 }
 
+GATE_MUTANTS = {
+    "gate_weights_swapped": ("out[i] = g * a[i] + (1.0 - g) * elem(&other, b, h, n, c);",
+                             "out[i] = (1.0 - g) * a[i] + g * elem(&other, b, h, n, c);"),
+    "gate_in_variance": ("return sigma_data / (sigma_data + sigma);",
+                         "return sigma_data * sigma_data / (sigma_data * sigma_data + sigma * sigma);"),
+    "gate_wrong_batch": ("const double g = oracle_noise_gate(sigma[b], sigma_data);",
+                         "const double g = oracle_noise_gate(sigma[0], sigma_data);"),
+    "mix_drops_other": ("out[i] = g * a[i] + (1.0 - g) * elem(&other, b, h, n, c);",
+                        "out[i] = g * a[i];"),
+}
+
 TILE_MUTANTS = {
     "hann_not_squared": ("  return sn * sn;", "  return sn;"),
     "hann_no_half_offset": ("((double)u + 0.5)", "((double)u)"),
@@ -153,3 +164,44 @@ def test_planted_tile_mistake_is_caught(tmp_path, name):
     assert text.count(old) == 1, "mutation site not unique: " + name
     so = _build(tmp_path, text.replace(old, new), name)
     assert _with_tile_library(so), "no pin caught the planted mistake " + name
+
+
+def _gate_pins():
+    """Names of the noise-gate pins that fail for the loaded oracle."""
+    import math
+    failed = []
+    special = pytest.importorskip("scipy.special")
+    for s in (0.01, 0.3, 2.0, 40.0):
+        if abs(oracle.noise_gate(s, 0.5) - special.expit(math.log(0.5 / s))) > 1e-15:
+            failed.append("logistic")
+            break
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((3, 1, 5, 4))
+    other = rng.standard_normal((3, 1, 5, 4))
+    out = oracle.gated_mix(a, other, [0.0, 0.5, math.inf], 0.5)
+    if not (np.array_equal(out[0], a[0]) and np.allclose(out[1], 0.5 * (a[1] + other[1]), rtol=1e-15)
+            and np.array_equal(out[2], other[2])):
+        failed.append("fixed_points")
+    return failed
+
+
+def _with_gate_library(path):
+    prev = oracle.use_library(path)
+    try:
+        return _gate_pins()
+    finally:
+        oracle.restore_library(prev)
+
+
+def test_unmodified_oracle_passes_gate_pins(tmp_path):
+    so = _build(tmp_path, open(SRC).read(), "pristine_gate")
+    assert _with_gate_library(so) == []
+
+
+@pytest.mark.parametrize("name", sorted(GATE_MUTANTS))
+def test_planted_gate_mistake_is_caught(tmp_path, name):
+    old, new = GATE_MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not unique: " + name
+    so = _build(tmp_path, text.replace(old, new), name)
+    assert _with_gate_library(so), "no pin caught the planted mistake " + name
