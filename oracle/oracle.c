@@ -20,9 +20,12 @@
  * the paper's spatial self-attention over all tokens of a frame sequence
  * requires (Sec. III-B).
  *
- * parity unpinned: the paper prints no value of this computation; the pins
- * are mathematical (brute-force quadratic form, closed forms, invariants,
- * finite differences), kept in the tests.
+ * Pins: the paper prints no value of this computation, so every function
+ * here is pinned to mathematics instead (tests/test_oracle*.py): the
+ * brute-force quadratic form, a hand-derived example with exact rational
+ * values, closed forms for degenerate inputs, invariances, central finite
+ * differences and autograd of the quadratic form, and planted mistakes
+ * that must each fail one of those pins.
  */
 #include "oracle.h"
 
