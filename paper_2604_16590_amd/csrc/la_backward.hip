@@ -607,10 +607,10 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 // 16-token tiles in turn (128 tokens per step).  Each wave does the query
 // pass for its tile and makes its tile's token-major operands (as in
 // bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
-// accumulates the dS row block w over all eight tiles (four 32-token
-// contractions), so its share of the partial is 8 tiles (32 registers)
-// instead of the whole 128 x 128.  dz is summed per wave and added across
-// the waves at the end.
+// accumulates a 2 x 4 patch of the 8 x 8 dS tile grid over all eight tiles
+// (four 32-token contractions), so its share of the partial is 8 tiles (32
+// registers) instead of the whole 128 x 128.  dz = sum_i dden_i phi(q_i)
+// rides along as one more column block of the same products.
 // ---------------------------------------------------------------------------
 template <int OT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
@@ -634,9 +634,8 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   // token-major operands of a 32-token contraction: tiles 2*kap and
   // 2*kap + 1 write the low and high halves of one 16-byte slot per lane,
   // so a slot is one operand (one LDS read)
-  __shared__ u32x4 xa[NW / 2][NB][64];  // phi(q)/den of block i
-  __shared__ u32x4 xb[NW / 2][NB][64];  // G of block j
-  __shared__ float dzs[NW][D];
+  __shared__ u32x4 xa[NW / 2][NB][64];      // phi(q)/den of block i
+  __shared__ u32x4 xb[NW / 2][NB + 1][64];  // G of block j; block NB: -G.O (hi, lo)
   const u32x4* zimg = simg + IMG_WORDS;
 
   const int bh = blockIdx.y;
@@ -682,12 +681,18 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
   }
 
-  f32x4 ds[NB];  // rows of block `wave`
+  // wave w accumulates the 2 x 4 patch of dS blocks with rows i0, i0 + 1
+  // and columns j0 .. j0 + 3; the waves of the left half also take the
+  // column block NB, whose columns 0 and 1 sum to dz (see the step)
+  const int i0 = 2 * (wave >> 1), j0 = 4 * (wave & 1);
+  const bool has_dz = (wave & 1) == 0;
+  f32x4 ds[2][4], dzb[2];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) ds[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float zacc[Q4];  // dz partial sums per run position over this wave's tokens
+  for (int ii = 0; ii < 2; ++ii) {
+    dzb[ii] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int c = 0; c < Q4; ++c) zacc[c] = 0.f;
+    for (int jj = 0; jj < 4; ++jj) ds[ii][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
 
   auto step = [&](int k, const Regs& x) {
     const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
@@ -722,18 +727,28 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
                                  sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
       ((u32x2*)&xb[wave >> 1][j][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
-    // per token: G . O, dQ, scales
+    const bool ok = tb + n < t_end;
+    const double rden = 1.0 / (double)dacc[0];
+    const float rd = ok ? (float)rden : 0.f;  // zero past the end: no dS, dz share
+    // G . O = phi(q) . X / den per token
     float gn = 0.f;
 #pragma unroll
     for (int i = 0; i < NT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) gn += run_val<DT_BF16>(pq, 4 * i + r) * acc[i][r];
     gn = sum_groups(gn);
-    const bool ok = tb + n < t_end;
-    const double rden = 1.0 / (double)dacc[0];
-    const float rd = ok ? (float)rden : 0.f;  // zero past the end: no dS, dz share
     const float go = gn * rd;
-    const float dd = -go * rd;  // dden
+    // dz = sum_i dden_i phi(q_i) = sum_i (phi(q_i)/den_i)(-G_i . O_i): one
+    // more column block of the dS product, whose B operand holds -G.O of
+    // each token as a bf16 pair hi + lo in columns 0 and 1 (made
+    // token-major by the same selection product)
+    {
+      const float hi = bf16f(to_bf16(-go));
+      const uint32_t w0 = g == 0 ? pack_bf16(hi, -go - hi) : 0u;
+      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{w0, 0u, 0u, 0u}), sel[0], f32x4{0.f, 0.f, 0.f, 0.f});
+      ((u32x2*)&xb[wave >> 1][NB][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+    }
+    // dQ
     char* orow = oh + tb * orow_bytes + ooff;
 #pragma unroll
     for (int w = 0; w < NCH; ++w) {
@@ -756,9 +771,6 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       }
       if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
     }
-    // dz += dden phi(q) (per lane, this lane's token)
-#pragma unroll
-    for (int c = 0; c < Q4; ++c) zacc[c] = fmaf(dd, run_val<DT_BF16>(pq, c), zacc[c]);
     // token-major phi(q)/den into LDS
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -774,47 +786,62 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     __syncthreads();
-    // dS rows of block `wave` over the eight tiles: tiles (2k, 2k + 1)
-    // make one 32-token contraction
+    // the wave's dS patch (and dz columns) over the eight tiles: tiles
+    // (2k, 2k + 1) make one 32-token contraction
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
-      const bf16x8 aa = as_bf16x8(xa[kap][wave][lane]);
+      const bf16x8 a0 = as_bf16x8(xa[kap][i0][lane]);
+      const bf16x8 a1 = as_bf16x8(xa[kap][i0 + 1][lane]);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) ds[j] = mfma_bf16(aa, as_bf16x8(xb[kap][j][lane]), ds[j]);
+      for (int jj = 0; jj < 4; ++jj) {
+        const bf16x8 bb = as_bf16x8(xb[kap][j0 + jj][lane]);
+        ds[0][jj] = mfma_bf16(a0, bb, ds[0][jj]);
+        ds[1][jj] = mfma_bf16(a1, bb, ds[1][jj]);
+      }
+      if (has_dz) {
+        const bf16x8 bz = as_bf16x8(xb[kap][NB][lane]);
+        dzb[0] = mfma_bf16(a0, bz, dzb[0]);
+        dzb[1] = mfma_bf16(a1, bz, dzb[1]);
+      }
     }
     __syncthreads();  // before the next step rewrites xa, xb
   };
 
+  // two register sets in turn: the next step's inputs are in flight while
+  // this step computes.  The loads are unconditional and the loop body has
+  // no early exit (a step past the end reads the partial's last row and
+  // adds nothing, see load and step), so the compiler's wait counts cover
+  // only the set a step is about to use; an odd step count runs one such
+  // empty step.  The scheduling barriers keep each load at the start of
+  // the step before its use (the scheduler would otherwise sink it).
   Regs ra, rb;
   load(0, ra);
   for (int k = 0; k < nsteps; k += 2) {
-    if (k + 1 < nsteps) load(k + 1, rb);
+    load(k + 1, rb);
+    __builtin_amdgcn_sched_barrier(0);
     step(k, ra);
-    if (k + 1 >= nsteps) break;
-    if (k + 2 < nsteps) load(k + 2, ra);
+    load(k + 2, ra);
+    __builtin_amdgcn_sched_barrier(0);
     step(k + 1, rb);
   }
 
-  // the workgroup's partial: this wave's row blocks, then dz over all waves
+
+  // the workgroup's partial: each wave's dS patch, and dz (the sum of
+  // columns 0 and 1 of block NB: lanes n = 0 and 1) from the left half
   float* out = part + ((int64_t)bh * P + p) * E;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) *(f32x4*)(out + ((wave * NB + j) * 64 + lane) * 4) = ds[j];
-  // dz: each run position summed over the 16 tokens (lanes n) of the group
+  for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-  for (int c = 0; c < Q4; ++c) {
-    float v = zacc[c];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
-    if (n == 0) dzs[wave][RN::feature(g, c)] = v;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < D; c += 512) {
-    float v = 0.f;
+    for (int jj = 0; jj < 4; ++jj)
+      *(f32x4*)(out + (((i0 + ii) * NB + j0 + jj) * 64 + lane) * 4) = ds[ii][jj];
+  if (has_dz) {
 #pragma unroll
-    for (int w = 0; w < NW; ++w) v += dzs[w][c];
-    out[D * D + c] = v;
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = dzb[ii][r] + __shfl_xor(dzb[ii][r], 1);
+        if (n == 0) out[D * D + 16 * (i0 + ii) + 4 * g + r] = v;
+      }
   }
 }
 

@@ -439,7 +439,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const char* qh = (const char*)q + (b * sb + h * sh) * ES;
   char* oh = (char*)o + (b * osb + h * osh) * OES;
   using RN = Run<D, DT>;
-  const uint32_t qoff = (uint32_t)n * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
   const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * RN::CH * OES);
 
   // the gate: spatial weight gw, the other branch's weight hw
@@ -463,28 +462,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   auto load_x = [&](int64_t tb, uint32_t* xw) {
     load_out_run<D, DT, OT>(xh + tb * orow_bytes + ooff, xw);
   };
-  auto load_one = [&](int tt, int64_t tb, QRegs& r) {
-    load_run<D, DT>(qh + tb * row_bytes + qoff, r.q[tt]);
-    if constexpr (XPF) load_x(tb, r.x[tt]);
-  };
+  // Rows past the range's end read its last row again (no zero fill and
+  // no branch around the loads); their results are not stored.
   auto load_q = [&](int64_t t0, QRegs& r) {
-    if (t0 + 16 * TT <= wg_end) {
 #pragma unroll
-      for (int tt = 0; tt < TT; ++tt) load_one(tt, t0 + 16 * tt, r);
-    } else {
-#pragma unroll
-      for (int tt = 0; tt < TT; ++tt) {
-        if (t0 + 16 * tt + n < wg_end) {
-          load_one(tt, t0 + 16 * tt, r);
-        } else {
-#pragma unroll
-          for (int w = 0; w < QW; ++w) r.q[tt][w] = 0;
-          if constexpr (XPF) {
-#pragma unroll
-            for (int w = 0; w < XW; ++w) r.x[tt][w] = 0;
-          }
-        }
-      }
+    for (int tt = 0; tt < TT; ++tt) {
+      const int64_t tb = min(t0 + 16 * tt, wg_end - 1);  // wave-uniform
+      const uint32_t row = (uint32_t)min(n, (int)min((int64_t)15, wg_end - 1 - tb));
+      load_run<D, DT>(qh + tb * row_bytes + (row * (uint32_t)row_bytes + (uint32_t)(g * RN::CB)),
+                      r.q[tt]);
+      if constexpr (XPF)
+        load_out_run<D, DT, OT>(
+            xh + tb * orow_bytes + (row * (uint32_t)orow_bytes + (uint32_t)(g * RN::CH * OES)),
+            r.x[tt]);
     }
   };
 
@@ -586,20 +576,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   };
 
   // two register sets in turn: the next step's queries are in flight in
-  // one while the other's step computes (no copies between them)
+  // one while the other's step computes (no copies between them).  The
+  // loads are unconditional and the loop body has no early exit, so the
+  // compiler's wait counts cover only the set a step is about to use (an
+  // odd step count runs one step with nothing to store); the scheduling
+  // barriers keep each load ahead of the step that overlaps it.
   constexpr int STRIDE = 16 * TT * 4;
-  QRegs qa, qb;
-  int64_t t0 = wg_begin + 16 * TT * wave;
-  if (t0 < wg_end) load_q(t0, qa);
-  while (t0 < wg_end) {
-    const int64_t t1 = t0 + STRIDE;
-    if (t1 < wg_end) load_q(t1, qb);
-    compute(t0, qa);
-    if (t1 >= wg_end) break;
-    const int64_t t2 = t1 + STRIDE;
-    if (t2 < wg_end) load_q(t2, qa);
-    compute(t1, qb);
-    t0 = t2;
+  const int64_t first = wg_begin + 16 * TT * wave;
+  const int nk = first < wg_end ? (int)((wg_end - first + STRIDE - 1) / STRIDE) : 0;
+  if (nk > 0) {
+    QRegs qa, qb;
+    load_q(first, qa);
+    for (int k = 0; k < nk; k += 2) {
+      load_q(first + (int64_t)(k + 1) * STRIDE, qb);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(first + (int64_t)k * STRIDE, qa);
+      load_q(first + (int64_t)(k + 2) * STRIDE, qa);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(first + (int64_t)(k + 1) * STRIDE, qb);
+    }
   }
 }
 
