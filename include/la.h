@@ -257,6 +257,14 @@ typedef struct {
                                      fake_slice_ns after launch (budget, FIFO
                                      and slicing logic only) */
   int64_t fake_slice_ns;
+  int32_t max_slices_per_request; /* 0 = strict FIFO: the oldest request takes
+                                     every slot and as much budget as it can;
+                                     k > 0 = a request holds at most k slots and
+                                     each of its slices at most budget/max_slots
+                                     bytes (one member at least), and when it
+                                     holds k the next requests in arrival order
+                                     are served, so a long request does not
+                                     hold back the short ones behind it */
 } la_server_config;
 
 typedef struct {

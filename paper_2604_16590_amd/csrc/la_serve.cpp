@@ -2,7 +2,9 @@
 //
 // One scheduler thread per server.  Each tick it retires finished slices,
 // then admits slices of the oldest request while a slot is free and the
-// slice's device memory fits the free part of the HBM budget.  A slice is a
+// slice's device memory fits the free part of the HBM budget (with a
+// per-request cap on slots, the next requests in arrival order take the
+// slots the oldest one may not).  A slice is a
 // contiguous run of the request's members (ensemble members are independent
 // problems with the same N, H, d), so the members of a large request can
 // run as memory frees up while other requests' slices overlap on the
@@ -294,15 +296,21 @@ int retire(la_server* s) {
   return n;
 }
 
-// Admit slices of the FIFO head while a slot and budget allow.
+// Admit slices in arrival order while a slot and budget allow.  With a cap
+// on slices per request, a request holding its cap is passed over for the
+// next one in the queue; budget shortage always stops admission (so a large
+// request is never starved by smaller ones behind it).
 int admit(la_server* s) {
   int n = 0;
   if (s->paused && !s->stopping) return 0;
-  while (!s->fifo.empty() && (int)s->inflight.size() < s->cfg.max_slots) {
-    const uint64_t id = s->fifo.front();
+  const int cap = s->cfg.max_slices_per_request;
+  auto fit = s->fifo.begin();
+  while (fit != s->fifo.end() && (int)s->inflight.size() < s->cfg.max_slots) {
+    const uint64_t id = *fit;
     auto it = s->reqs.find(id);
-    if (it == s->reqs.end()) { s->fifo.pop_front(); continue; }
+    if (it == s->reqs.end()) { fit = s->fifo.erase(fit); continue; }
     Request& rq = it->second;
+    if (cap > 0 && rq.slices_started - rq.slices_done >= cap) { ++fit; continue; }
     const la_request& r = rq.spec;
     if (!rq.keep_held) {
       size_t off;
@@ -321,11 +329,16 @@ int admit(la_server* s) {
       else
         rq.o = r.o;
     }
-    // largest member count that fits the biggest free block
+    // largest member count that fits the biggest free block (and, with a
+    // per-request cap, this request's share of the budget)
     int64_t left = r.desc.B - rq.next_member;
     int64_t m = left;
     if (s->cfg.max_members_per_slice > 0) m = std::min<int64_t>(m, s->cfg.max_members_per_slice);
-    const size_t room = s->arena.largest_free();
+    size_t room = s->arena.largest_free();
+    if (cap > 0) {
+      const size_t share = std::max<size_t>(s->cfg.hbm_budget_bytes / s->cfg.max_slots, slice_bytes(r, 1));
+      room = std::min(room, share);
+    }
     while (m > 0 && slice_bytes(r, m) > room) m = m > 8 ? m * 3 / 4 : m - 1;
     if (m <= 0) break;
     Slice sl{};
@@ -353,13 +366,14 @@ int admit(la_server* s) {
     }
     rq.next_member += m;
     rq.slices_started += 1;
-    if (rq.next_member >= r.desc.B) s->fifo.pop_front();
+    const bool all_admitted = rq.next_member >= r.desc.B;
     const la_status st = launch_slice(s, rq, sl);
     if (st != LA_OK) {
       finish_slice(s, sl, false);
     } else {
       s->inflight.push_back(sl);
     }
+    if (all_admitted) fit = s->fifo.erase(fit);
     ++n;
   }
   return n;
@@ -388,7 +402,8 @@ extern "C" {
 la_status la_serve_create(const la_server_config* cfg, la_server** out) {
   if (!cfg || !out) return LA_ERR_INVALID_ARG;
   if (cfg->max_slots < 1 || cfg->n_streams < 1 || cfg->hbm_budget_bytes < kAlign ||
-      cfg->max_members_per_slice < 0 || cfg->fake_slice_ns < 0)
+      cfg->max_members_per_slice < 0 || cfg->fake_slice_ns < 0 ||
+      cfg->max_slices_per_request < 0)
     return LA_ERR_INVALID_ARG;
   la_server* s = new la_server();
   s->cfg = *cfg;

@@ -18,7 +18,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("max_slots", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("max_members_per_slice", ctypes.c_int32), ("fake_executor", ctypes.c_int32),
-                ("fake_slice_ns", ctypes.c_int64)]
+                ("fake_slice_ns", ctypes.c_int64), ("max_slices_per_request", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -73,9 +73,10 @@ def desc_for(Bm, H, N, d, dtype=B.LA_BF16, out_dtype=None):
 
 class Server:
     def __init__(self, budget_bytes, max_slots=4, n_streams=4, max_members_per_slice=0,
-                 device=0, fake_slice_ns=None):
+                 device=0, fake_slice_ns=None, max_slices_per_request=0):
         cfg = ServerConfig(device, int(budget_bytes), max_slots, n_streams, max_members_per_slice,
-                           1 if fake_slice_ns is not None else 0, int(fake_slice_ns or 0))
+                           1 if fake_slice_ns is not None else 0, int(fake_slice_ns or 0),
+                           int(max_slices_per_request))
         h = ctypes.c_void_p()
         B._check("la_serve_create", _lib().la_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h
@@ -201,7 +202,7 @@ def bench_summary(budget_gb=200, n_requests=40):
     """Serving measurement for the benchmark: the literal 200 req/s Poisson
     stream (saturating; bounded window) and a point at 0.7x the measured
     saturated throughput."""
-    with Server(int(budget_gb * 1e9), max_slots=4, n_streams=4) as srv:
+    with Server(int(budget_gb * 1e9), max_slots=4, n_streams=4, max_slices_per_request=2) as srv:
         sat = run_poisson(srv, n_requests, 200.0, seed=5)
         cap = sat["req_per_s"] or 1.0
         sub = run_poisson(srv, n_requests, 0.7 * cap, seed=6)

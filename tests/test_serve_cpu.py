@@ -74,6 +74,38 @@ def test_slices_overlap_with_several_slots():
         assert wall < 60 * MS  # four 20 ms slices ran concurrently, not back to back
 
 
+@pytest.mark.parametrize("cap", [0, 1])
+def test_per_request_slot_cap_lets_short_requests_pass(cap):
+    # a long request of 8 one-member slices, then a short one: strict FIFO
+    # (cap 0) admits the short one only after every slice of the long one;
+    # with a cap of one slot per request it runs beside the long one
+    with serve.Server(1 << 30, max_slots=2, max_members_per_slice=1, fake_slice_ns=10 * MS,
+                      max_slices_per_request=cap) as srv:
+        srv.pause()
+        long_id = srv.submit(serve.desc_for(8, 1, 1024, 64), gen_seed=1)
+        short_id = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=2)
+        srv.pause(False)
+        rl, rs = srv.wait(long_id), srv.wait(short_id)
+        assert rl.state == serve.DONE and rs.state == serve.DONE and rl.slices == 8
+        if cap:
+            assert rs.t_done_ns < rl.t_done_ns
+            assert rs.t_admit_ns - rl.t_admit_ns < 5 * MS  # admitted at once
+        else:
+            assert rs.t_admit_ns - rl.t_admit_ns >= 25 * MS  # behind three rounds of slices
+
+
+def test_slot_cap_bounds_a_slice_to_its_budget_share():
+    H, N, d = 2, 65536, 64
+    per_member = member_bytes(H, N, d)
+    budget = 64 * per_member
+    with serve.Server(budget, max_slots=4, fake_slice_ns=MS, max_slices_per_request=2) as srv:
+        rid = srv.submit(serve.desc_for(16, H, N, d), gen_seed=3)
+        r = srv.wait(rid)
+        assert r.state == serve.DONE
+        # generated Q, K, V of 16 members = 48 member tensors > 64/4 = 16
+        assert r.slices >= 3
+
+
 def test_request_too_large_for_budget_is_rejected():
     with serve.Server(64 << 20, fake_slice_ns=MS) as srv:
         with pytest.raises(B.LaError) as e:
@@ -155,6 +187,8 @@ def test_concurrent_submitters():
 def test_invalid_config_and_request():
     with pytest.raises(B.LaError):
         serve.Server(1 << 30, max_slots=0, fake_slice_ns=MS)
+    with pytest.raises(B.LaError):
+        serve.Server(1 << 30, max_slices_per_request=-1, fake_slice_ns=MS)
     with serve.Server(1 << 30, fake_slice_ns=MS) as srv:
         bad = serve.desc_for(1, 1, 1024, 48)
         with pytest.raises(B.LaError) as e:
