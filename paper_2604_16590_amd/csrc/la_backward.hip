@@ -602,18 +602,19 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 }
 
 // ---------------------------------------------------------------------------
-// Fused query backward at d = 128 (bf16): the eight waves of a workgroup
-// (two per SIMD) share one partial (token range [p*Tw, p*Tw + Tw)), taking
-// 16-token tiles in turn (128 tokens per step).  Each wave does the query
-// pass for its tile and makes its tile's token-major operands (as in
+// Fused query backward at d = 128 (bf16): the four waves of a workgroup
+// share one partial (token range [p*Tw, p*Tw + Tw)), taking 16-token tiles
+// in turn (64 tokens per step); two workgroups fit a compute unit, so one
+// waiting at a barrier leaves the SIMDs to the other.  Each wave does the
+// query pass for its tile and makes its tile's token-major operands (as in
 // bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
-// accumulates a 2 x 4 patch of the 8 x 8 dS tile grid over all eight tiles
-// (four 32-token contractions), so its share of the partial is 8 tiles (32
-// registers) instead of the whole 128 x 128.  dz = sum_i dden_i phi(q_i)
-// rides along as one more column block of the same products.
+// accumulates dS row blocks 2w and 2w + 1 over the four tiles (two 32-token
+// contractions), so its share of the partial is 16 tiles (64 registers)
+// instead of the whole 128 x 128.  dz = sum_i dden_i phi(q_i) rides along
+// as one more column block of the same products.
 // ---------------------------------------------------------------------------
 template <int OT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, int64_t sb,
                      int64_t sh, int64_t sn, void* __restrict__ dq, int64_t osb, int64_t osh,
                      int64_t osn, int H, int64_t N, int P, int Tw, const void* __restrict__ img,
@@ -630,7 +631,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   constexpr int E = D * D + D;
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
   __shared__ float zf[D];
-  constexpr int NW = 8;             // waves (tiles per step)
+  constexpr int NW = 4;             // waves (tiles per step)
   // token-major operands of a 32-token contraction: tiles 2*kap and
   // 2*kap + 1 write the low and high halves of one 16-byte slot per lane,
   // so a slot is one operand (one LDS read)
@@ -644,7 +645,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     const char* head = (const char*)img + (int64_t)bh * IC::head_bytes(DT_BF16);
     stage_image(simg, (const u32x4*)(head + IC::img_bytes(DT_BF16)), IMG_WORDS, true);
     stage_image(simg + IMG_WORDS, (const u32x4*)(head + IC::mat_bytes(DT_BF16)), Z_WORDS, false);
-    for (int c = threadIdx.x; c < D; c += 512) zf[c] = (float)z64[(int64_t)bh * D + c];
+    for (int c = threadIdx.x; c < D; c += 64 * NW) zf[c] = (float)z64[(int64_t)bh * D + c];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = wave_index();
@@ -681,17 +682,18 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
   }
 
-  // wave w accumulates the 2 x 4 patch of dS blocks with rows i0, i0 + 1
-  // and columns j0 .. j0 + 3; the waves of the left half also take the
-  // column block NB, whose columns 0 and 1 sum to dz (see the step)
-  const int i0 = 2 * (wave >> 1), j0 = 4 * (wave & 1);
-  const bool has_dz = (wave & 1) == 0;
-  f32x4 ds[2][4], dzb[2];
+  // wave w accumulates dS row blocks i0, i0 + 1 (all NB column blocks)
+  // and the column block NB of those rows, whose columns 0 and 1 sum to
+  // dz (see the step)
+  constexpr int JW = NB;  // column blocks per wave
+  const int i0 = 2 * wave, j0 = 0;
+  constexpr bool has_dz = true;
+  f32x4 ds[2][JW], dzb[2];
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
     dzb[ii] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) ds[ii][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int jj = 0; jj < JW; ++jj) ds[ii][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 
   auto step = [&](int k, const Regs& x) {
@@ -793,7 +795,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       const bf16x8 a0 = as_bf16x8(xa[kap][i0][lane]);
       const bf16x8 a1 = as_bf16x8(xa[kap][i0 + 1][lane]);
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
+      for (int jj = 0; jj < JW; ++jj) {
         const bf16x8 bb = as_bf16x8(xb[kap][j0 + jj][lane]);
         ds[0][jj] = mfma_bf16(a0, bb, ds[0][jj]);
         ds[1][jj] = mfma_bf16(a1, bb, ds[1][jj]);
@@ -832,7 +834,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < JW; ++jj)
       *(f32x4*)(out + (((i0 + ii) * NB + j0 + jj) * 64 + lane) * 4) = ds[ii][jj];
   if (has_dz) {
 #pragma unroll
@@ -994,7 +996,7 @@ static void launch_rows(const BwdArgs& a) {
     dim3 fgrid((unsigned)a.P, BH);
     // (four waves with two tiles each, one wave per SIMD, measured slower:
     // 4.1 against 3.5 ms)
-    bwd_qds4_kernel<OT><<<fgrid, 512, 0, a.stream>>>(
+    bwd_qds4_kernel<OT><<<fgrid, 256, 0, a.stream>>>(
         a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
         a.img, a.z64, a.part);
     launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
