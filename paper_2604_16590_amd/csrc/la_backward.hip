@@ -788,7 +788,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     __syncthreads();
-    // the wave's dS patch (and dz columns) over the eight tiles: tiles
+    // the wave's dS rows (and dz columns) over the step's tiles: tiles
     // (2k, 2k + 1) make one 32-token contraction
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
@@ -991,11 +991,9 @@ static void launch_rows(const BwdArgs& a) {
   const int BH = (int)(a.B * a.H);
   dim3 grid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
   if constexpr (DT == DT_BF16 && D == 128) {
-    // one pass, eight waves sharing each partial
+    // one pass, four waves sharing each partial
     ProfScope prof("bwd_query_ds", a.stream);
     dim3 fgrid((unsigned)a.P, BH);
-    // (four waves with two tiles each, one wave per SIMD, measured slower:
-    // 4.1 against 3.5 ms)
     bwd_qds4_kernel<OT><<<fgrid, 256, 0, a.stream>>>(
         a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
         a.img, a.z64, a.part);
