@@ -608,10 +608,11 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 // waiting at a barrier leaves the SIMDs to the other.  Each wave does the
 // query pass for its tile and makes its tile's token-major operands (as in
 // bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
-// accumulates dS row blocks 2w and 2w + 1 over the four tiles (two 32-token
-// contractions), so its share of the partial is 16 tiles (64 registers)
-// instead of the whole 128 x 128.  dz = sum_i dden_i phi(q_i) rides along
-// as one more column block of the same products.
+// accumulates a 4 x 4 patch of the 8 x 8 grid of dS tiles over the four
+// tiles (two 32-token contractions), so its share of the partial is 16
+// tiles (64 registers) instead of the whole 128 x 128.  dz = sum_i dden_i
+// phi(q_i) rides along as one more column block of the same products (the
+// waves of the left column of patches take it).
 // ---------------------------------------------------------------------------
 template <int OT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
@@ -682,15 +683,15 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     sel[hh] = as_bf16x8(u32x4{w4[0], w4[1], w4[2], w4[3]});
   }
 
-  // wave w accumulates dS row blocks i0, i0 + 1 (all NB column blocks)
-  // and the column block NB of those rows, whose columns 0 and 1 sum to
-  // dz (see the step)
-  constexpr int JW = NB;  // column blocks per wave
-  const int i0 = 2 * wave, j0 = 0;
-  constexpr bool has_dz = true;
-  f32x4 ds[2][JW], dzb[2];
+  // wave w accumulates the 4 x 4 patch of dS tiles at (i0, j0); the waves
+  // with j0 = 0 also take the column block NB of their rows, whose columns
+  // 0 and 1 sum to dz (see the step)
+  constexpr int IW = 4, JW = 4;  // row and column blocks per wave
+  const int i0 = IW * (wave >> 1), j0 = JW * (wave & 1);
+  const bool has_dz = (wave & 1) == 0;
+  f32x4 ds[IW][JW], dzb[IW];
 #pragma unroll
-  for (int ii = 0; ii < 2; ++ii) {
+  for (int ii = 0; ii < IW; ++ii) {
     dzb[ii] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int jj = 0; jj < JW; ++jj) ds[ii][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -792,18 +793,19 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     // (2k, 2k + 1) make one 32-token contraction
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
-      const bf16x8 a0 = as_bf16x8(xa[kap][i0][lane]);
-      const bf16x8 a1 = as_bf16x8(xa[kap][i0 + 1][lane]);
+      bf16x8 aa[IW];
+#pragma unroll
+      for (int ii = 0; ii < IW; ++ii) aa[ii] = as_bf16x8(xa[kap][i0 + ii][lane]);
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) {
         const bf16x8 bb = as_bf16x8(xb[kap][j0 + jj][lane]);
-        ds[0][jj] = mfma_bf16(a0, bb, ds[0][jj]);
-        ds[1][jj] = mfma_bf16(a1, bb, ds[1][jj]);
+#pragma unroll
+        for (int ii = 0; ii < IW; ++ii) ds[ii][jj] = mfma_bf16(aa[ii], bb, ds[ii][jj]);
       }
       if (has_dz) {
         const bf16x8 bz = as_bf16x8(xb[kap][NB][lane]);
-        dzb[0] = mfma_bf16(a0, bz, dzb[0]);
-        dzb[1] = mfma_bf16(a1, bz, dzb[1]);
+#pragma unroll
+        for (int ii = 0; ii < IW; ++ii) dzb[ii] = mfma_bf16(aa[ii], bz, dzb[ii]);
       }
     }
     __syncthreads();  // before the next step rewrites xa, xb
@@ -832,13 +834,13 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   // columns 0 and 1 of block NB: lanes n = 0 and 1) from the left half
   float* out = part + ((int64_t)bh * P + p) * E;
 #pragma unroll
-  for (int ii = 0; ii < 2; ++ii)
+  for (int ii = 0; ii < IW; ++ii)
 #pragma unroll
     for (int jj = 0; jj < JW; ++jj)
       *(f32x4*)(out + (((i0 + ii) * NB + j0 + jj) * 64 + lane) * 4) = ds[ii][jj];
   if (has_dz) {
 #pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
+    for (int ii = 0; ii < IW; ++ii)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float v = dzb[ii][r] + __shfl_xor(dzb[ii][r], 1);
