@@ -233,8 +233,10 @@ la_status la_tile_blend(const la_tile_desc* desc, const void* tiles, void* field
  * d).  The server:
  *  - queues requests FIFO and splits each into member slices;
  *  - admits the next slice of the oldest request when a slot is free and
- *    the slice's device memory fits the free HBM budget (head-of-line
- *    order: a request never overtakes an older one);
+ *    the slice's device memory fits the free HBM budget; by default a
+ *    request never overtakes an older one, while with
+ *    max_slices_per_request a request holding that many slots leaves the
+ *    free ones to the next requests in arrival order;
  *  - runs each slice (optional input generation, summary, combine, apply)
  *    on one of its HIP streams, so slices of different requests overlap on
  *    the GPU;
