@@ -28,11 +28,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Two floats -> bfloat16 pair (lo in bits 0..15), round to nearest even:
+// one v_cvt_pk_bf16_f32 (the values here are finite, never NaN).
+__device__ __forceinline__ uint32_t bf16_pair_rne(float lo, float hi) {
+  typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16v2));
 }
 
 struct GenArgs {
@@ -46,6 +47,8 @@ struct GenArgs {
   int grid_T, grid_lat, grid_lon;
   float amplitude;
   int64_t b_offset;
+  int dshift;   // log2(d) when d is a power of two, else -1
+  int wide;     // four consecutive elements may be stored as one vector
 };
 
 // Grid term of channel c, head h, token n (FP32).
@@ -73,23 +76,31 @@ __device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float& z0, 
   z1 = r * s;
 }
 
+// Element value: mean + std z, plus the grid term.
+__device__ __forceinline__ float element(const GenArgs& a, int h, uint32_t n, uint32_t c, float z) {
+  float val = a.mean + a.std * z;
+  if (a.grid_T > 0) val += structure(a, h, n, c);
+  return val;
+}
+
+// (token, channel) of element e of a head.
+__device__ __forceinline__ void split(const GenArgs& a, uint32_t e, uint32_t& n, uint32_t& cc) {
+  if (a.dshift >= 0) {
+    n = e >> a.dshift;
+    cc = e & ((uint32_t)a.d - 1u);
+  } else {
+    n = e / (uint32_t)a.d;
+    cc = e - n * (uint32_t)a.d;
+  }
+}
+
 // Store elements (e0, e0 + 1) of a head at token n, channel cc.
 __device__ __forceinline__ void store_pair(const GenArgs& a, char* head, int h, uint32_t n,
                                            uint32_t cc, float z0, float z1) {
-  float f[2] = {z0, z1};
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    float val = a.mean + a.std * f[s];
-    if (a.grid_T > 0) val += structure(a, h, n, cc + s);
-    f[s] = val;
-  }
+  const float f0 = element(a, h, n, cc, z0), f1 = element(a, h, n, cc + 1, z1);
   const int64_t off = (int64_t)n * a.sn + cc;
-  if (a.dtype == 0) {
-    const uint32_t w = (uint32_t)f32_to_bf16_rne(f[0]) | ((uint32_t)f32_to_bf16_rne(f[1]) << 16);
-    *(uint32_t*)((uint16_t*)head + off) = w;
-  } else {
-    *(float2*)((float*)head + off) = float2{f[0], f[1]};
-  }
+  if (a.dtype == 0) *(uint32_t*)((uint16_t*)head + off) = bf16_pair_rne(f0, f1);
+  else *(float2*)((float*)head + off) = float2{f0, f1};
 }
 
 // Grid: y = (b, h) of the filled tensor, x strides over the head's element
@@ -115,9 +126,23 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
       box_muller(c[0], c[1], z0, z1);
       box_muller(c[2], c[3], z2, z3);
       const uint32_t e0 = (uint32_t)(4 * ql);  // element within the head (N * d < 2^32)
-      const uint32_t n = e0 / d, cc = e0 - n * d;
-      store_pair(a, head, (int)h, n, cc, z0, z1);
-      store_pair(a, head, (int)h, n, cc + 2, z2, z3);
+      uint32_t n, cc;
+      split(a, e0, n, cc);
+      if (a.wide) {
+        // the four elements are consecutive in one row: one 8- or 16-byte store
+        const float f0 = element(a, (int)h, n, cc, z0), f1 = element(a, (int)h, n, cc + 1, z1);
+        const float f2 = element(a, (int)h, n, cc + 2, z2), f3 = element(a, (int)h, n, cc + 3, z3);
+        const int64_t off = (int64_t)n * a.sn + cc;
+        if (a.dtype == 0) {
+          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+          *(u32x2*)((uint16_t*)head + off) = u32x2{bf16_pair_rne(f0, f1), bf16_pair_rne(f2, f3)};
+        } else {
+          *(float4*)((float*)head + off) = float4{f0, f1, f2, f3};
+        }
+      } else {
+        store_pair(a, head, (int)h, n, cc, z0, z1);
+        store_pair(a, head, (int)h, n, cc + 2, z2, z3);
+      }
     }
   } else {
     for (int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pl < head_pairs; pl += stride) {
@@ -129,7 +154,8 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs a) {
       if (lp & 1) box_muller(c[2], c[3], z0, z1);
       else box_muller(c[0], c[1], z0, z1);
       const uint32_t e0 = (uint32_t)(2 * pl);
-      const uint32_t n = e0 / d, cc = e0 - n * d;
+      uint32_t n, cc;
+      split(a, e0, n, cc);
       store_pair(a, head, (int)h, n, cc, z0, z1);
     }
   }
@@ -159,6 +185,11 @@ extern "C" int32_t la_gen_fill(void* dst, int32_t dtype, int64_t B, int64_t H, i
   a.amplitude = (float)spec->amplitude;
   a.b_offset = spec->b_offset;
   if (a.b_offset < 0) return 1;
+  a.dshift = -1;
+  for (int k = 0; k < 31; ++k)
+    if ((int64_t(1) << k) == d) a.dshift = k;
+  // four-element vectors stay aligned when every stride is a multiple of 4
+  a.wide = (d % 4 == 0) && sb % 4 == 0 && sh % 4 == 0 && sn % 4 == 0;
   const int64_t head_pairs = N * d / 2;
   int64_t bx = (head_pairs + 255) / 256;
   const int64_t cap = std::max<int64_t>(1, 16384 / (B * H));  // ~16K blocks in total
