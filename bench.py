@@ -135,7 +135,7 @@ def traffic_for(kernel):
 
 
 def other_workloads(steps):
-    """tokens/s of the same path at the task's other bf16 shapes: the
+    """tokens/s of the same path at the other bf16 workload shapes: the
     fwd+bwd shape at d = 64 (B2 H16, T64 x 64 x 64 = 262,144 tokens) and the
     grid forward (B4 H16, T8 x 32 x 64 = 16,384 tokens, d = 64)."""
     import torch
@@ -260,7 +260,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(token shards would exchange one (S, z) sum per pass); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)

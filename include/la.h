@@ -46,7 +46,7 @@ extern "C" {
 typedef enum {
   LA_OK = 0,
   LA_ERR_INVALID_ARG = 1, /* null/misaligned pointer, bad size or stride   */
-  LA_ERR_UNSUPPORTED = 2, /* valid request this build does not implement    */
+  LA_ERR_UNSUPPORTED = 2, /* valid request the library does not implement   */
   LA_ERR_OOM = 3,         /* workspace too small, or HBM budget exceeded    */
   LA_ERR_HIP = 4,         /* a HIP runtime call failed; see la_last_hip_error */
   LA_ERR_NOT_FOUND = 5,   /* unknown request id                             */

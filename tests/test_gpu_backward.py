@@ -162,7 +162,7 @@ def test_backward_bitwise_deterministic():
         assert torch.equal(x, y)
 
 
-def test_config4_full_size_sampled_heads():
+def test_fwd_bwd_d64_262144_tokens_sampled_heads():
     # N = 262,144 (T64 x 64 x 64), B2 H16 d64, bf16, upstream gradient N(0,1);
     # the oracle recomputes two whole heads.
     dev = require_gpu()
@@ -179,17 +179,17 @@ def test_config4_full_size_sampled_heads():
         rq, rk, rv = oracle.backward(*host)
         for name, x, r in (("dq", q.grad, rq), ("dk", k.grad, rk), ("dv", v.grad, rv)):
             err = normwise(as64(x[b:b + 1, h:h + 1]), r)
-            print("config4 head", (b, h), name, err, flush=True)
+            print("B2 H16 N262144 d64 head", (b, h), name, err, flush=True)
             assert err < TOL["bf16"]
     # at any size: sum_j dV_j = sum_i G_i per (b, h, feature)
     lhs = v.grad.double().sum(2)
     rhs = g.double().sum(2)
     rel = ((lhs - rhs).norm(dim=-1) / rhs.norm(dim=-1)).max().item()
-    print("config4 column-sum identity", rel)
+    print("B2 H16 N262144 d64 column-sum identity", rel)
     assert rel < TOL["bf16"]
 
 
-def test_config3_long_context_fwd_bwd_sampled_rows():
+def test_long_context_2m_tokens_fwd_bwd_sampled_rows():
     # 2,097,152 tokens, B1 H8 d128, bf16: one head checked against the
     # oracle (exact S, z, dS, dz over all tokens; dQ/dK/dV on sampled rows).
     dev = require_gpu()
@@ -211,7 +211,7 @@ def test_config3_long_context_fwd_bwd_sampled_rows():
     idx = torch.from_numpy(rows).to(dev)
     for name, x, r in (("dq", dq, rdq), ("dk", dk, rdk), ("dv", dv, rdv)):
         err = normwise(as64(x[:, h:h + 1, idx]), r)
-        print("config3 bwd", name, err, max_rel(as64(x[:, h:h + 1, idx]), r), flush=True)
+        print("long-context bwd", name, err, max_rel(as64(x[:, h:h + 1, idx]), r), flush=True)
         assert err < TOL["bf16"]
     lhs = dv.double().sum(2)
     rhs = xs[3].double().sum(2)

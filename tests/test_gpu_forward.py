@@ -40,7 +40,7 @@ def check(shape, dtype, seed, out_dtype=None, std=1.0, grid=None):
     return err
 
 
-def test_config1_fp32_vs_quadratic_form():
+def test_fp32_4096_tokens_vs_quadratic_form():
     # B1 H1 N4096 d64 fp32 N(0,1), checked against the brute-force form
     q, k, v = make_inputs((1, 1, 4096, 64), "fp32", 1000)
     o = run_forward(q, k, v)
@@ -49,7 +49,7 @@ def test_config1_fp32_vs_quadratic_form():
     A = ph(Q[0, 0]) @ ph(K[0, 0]).T
     ref = (A @ V[0, 0]) / A.sum(1, keepdims=True)
     err = normwise(as64(o), ref[None, None])
-    print("config1 normwise error", err, "max rel", max_rel(as64(o), ref[None, None]))
+    print("fp32 N4096 normwise error", err, "max rel", max_rel(as64(o), ref[None, None]))
     assert err < TOL["fp32"]
 
 
@@ -78,14 +78,14 @@ def test_fp32_in_bf16_out():
     assert normwise(as64(o), oracle.forward(q, k, v)) < TOL["bf16"]
 
 
-def test_config2_spatiotemporal_grid_full_size():
+def test_spatiotemporal_grid_16384_tokens_full_size():
     # T8 x 32 x 64 = 16384 tokens, B4 H16 d64, bf16, N(0,1) + grid structure
     shape, grid = (4, 16, 16384, 64), (8, 32, 64)
     q, k, v = make_inputs(shape, "bf16", 1001, grid=grid)
     o = run_forward(q, k, v)
     o_ref = oracle.forward(q, k, v)
     err = normwise(as64(o), o_ref)
-    print("config2 normwise", err, "max rel", max_rel(as64(o), o_ref))
+    print("grid normwise", err, "max rel", max_rel(as64(o), o_ref))
     assert err < TOL["bf16"]
 
 
@@ -191,7 +191,7 @@ def test_generator_matches_host_definition():
             assert np.mean(dv == hv) > (0.97 if dtype == "bf16" else 0.5)
 
 
-def test_config3_long_context_sampled_heads():
+def test_long_context_2m_tokens_sampled_heads():
     # T256 x 64 x 128 = 2,097,152 tokens, B1 H8 d128, bf16, N(0, var 0.5),
     # in the launch configuration the benchmark times.  The oracle checks
     # two whole heads (all N keys for S, z; sampled queries for O).
@@ -214,7 +214,7 @@ def test_config3_long_context_sampled_heads():
         qh = to_host(xs[0][:, h:h + 1])[:, :, rows]
         o_ref = oracle.apply(np.ascontiguousarray(qh), S_ref, z_ref)
         err = normwise(as64(o[:, h:h + 1, torch.from_numpy(rows).to(dev)]), o_ref)
-        print("config3 head", h, "normwise", err, flush=True)
+        print("long-context head", h, "normwise", err, flush=True)
         assert err < TOL["bf16"]
     # convex hull of V holds at any size: min_j v <= O <= max_j v per feature
     vmin = xs[2].float().amin(dim=2, keepdim=True)
