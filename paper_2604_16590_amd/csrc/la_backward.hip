@@ -702,7 +702,8 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     uint32_t pq[RW];
     phi_words<DT_BF16, D>(x[0], pq);
     const uint32_t* pg = x[1];
-    // X = S G (hi + lo) and den = phi(q) . z (z tile) for the tile
+    // X = S G (S as its bf16 hi part) and den = phi(q) . z (the z tile,
+    // hi + lo) for the tile
     f32x4 acc[NT], dacc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -789,7 +790,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     __syncthreads();
-    // the wave's dS rows (and dz columns) over the step's tiles: tiles
+    // the wave's dS patch (and dz columns) over the step's tiles: tiles
     // (2k, 2k + 1) make one 32-token contraction
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
@@ -828,7 +829,6 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
     __builtin_amdgcn_sched_barrier(0);
     step(k + 1, rb);
   }
-
 
   // the workgroup's partial: each wave's dS patch, and dz (the sum of
   // columns 0 and 1 of block NB: lanes n = 0 and 1) from the left half
@@ -1003,7 +1003,7 @@ static void launch_rows(const BwdArgs& a) {
   } else if constexpr (DT == DT_BF16 && (D == 32 || D == 64)) {
     // one pass: dQ and the per-wave partials of dS, dz (at d = 128 the
     // whole partial dS plus the query pass's state exceed the registers of
-    // one wave, and the two-pass form is faster)
+    // one wave, so there four waves share a partial, above)
     ProfScope prof("bwd_query_ds", a.stream);
     dim3 fgrid((unsigned)((a.P + 3) / 4), BH);
     bwd_qds_kernel<OT, D><<<fgrid, 256, 0, a.stream>>>(

@@ -3,7 +3,8 @@
 //
 // Forward of kernelised linear attention per (b, h):
 //   S = phi(K)^T V, z = phi(K)^T 1 over all N tokens (summary_kernel, then
-//   combine_kernel), O_i = phi(q_i)^T S / (phi(q_i) . z) (apply_kernel).
+//   combine_kernel), O_i = phi(q_i)^T S / (phi(q_i) . z) (apply_kernel,
+//   which can also blend O with another branch's output by a noise gate).
 // Both phases stream HBM once: summary reads K and V, apply reads Q and
 // writes O.  The d x d contractions run on the matrix cores.
 #include "la_kernels.h"
