@@ -27,7 +27,10 @@ def fetch(res, Bm, H, N, d):
     return o, S, z
 
 
-def test_alone_equals_mix_and_matches_oracle():
+@pytest.mark.parametrize("cap", [0, 1])
+def test_alone_equals_mix_and_matches_oracle(cap):
+    # cap: slots one request may hold in the mix (0: strict FIFO; 1: the
+    # requests behind the target run beside it)
     require_gpu()
     H, d = 4, 64
     target = (6, 20000)  # members, tokens
@@ -38,7 +41,8 @@ def test_alone_equals_mix_and_matches_oracle():
         alone = fetch(r, target[0], H, target[1], d)
         srv.release(rid)
     # in a mix, with a budget and slice cap that split the target differently
-    with serve.Server(2 << 30, max_slots=3, n_streams=3, max_members_per_slice=2) as srv:
+    with serve.Server(2 << 30, max_slots=3, n_streams=3, max_members_per_slice=2,
+                      max_slices_per_request=cap) as srv:
         others = [srv.submit(serve.desc_for(3, H, n, d), gen_seed=s)
                   for s, n in ((1, 50000), (2, 7777))]
         rid = srv.submit(serve.desc_for(target[0], H, target[1], d), gen_seed=99)
