@@ -42,11 +42,25 @@ KERNEL_PASSES = {
     "bwd_query_ds": 3,  # fused: read Q, dO; write dQ (and the dS, dz partials)
     "bwd_key": 4,       # read K, V; write dK, dV
 }
-# matrix-core FLOPs per launch, in units of 2*B*H*N*d^2 (the method's
-# products only: S hi + lo counts 2; operand re-layout products are not
-# counted)
-KERNEL_MMA = {"summary_fwd": 1, "apply": 2, "bwd_query": 2, "summary_bwd": 1, "bwd_query_ds": 3,
-              "bwd_key": 2}
+
+
+def kernel_mma(dtype, d):
+    """Matrix-core FLOPs per launch of each kernel, in units of 2*B*H*N*d^2.
+
+    Only the method's products count (operand re-layout products do not).
+    bf16 applies S (and, in the query backward, S again) as two operands
+    hi + lo, so those products count twice; the fused query backward at
+    d = 128 uses the hi part only.  fp32 applies S as one fp32 operand.
+    """
+    two = 2 if dtype == "bf16" else 1
+    return {"summary_fwd": 1, "apply": two, "bwd_query": two, "summary_bwd": 1,
+            "bwd_query_ds": (1 if d >= 128 else 2) + 1, "bwd_key": 2}
+
+
+def mma_flops_per_step(kernels, dtype, elems, d):
+    table = kernel_mma(dtype, d)
+    return sum(table[k] * kernels[k]["launches_per_step"] * 2 * elems * d
+               for k in table if k in kernels)
 
 
 def parse():
@@ -316,8 +330,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
     # what the kernels that ran must move and multiply, per step
-    mma_flops = sum(KERNEL_MMA[k] * kernels[k]["launches_per_step"] * 2 * elems * w["d"]
-                    for k in KERNEL_MMA if k in kernels)
+    mma_flops = mma_flops_per_step(kernels, "bf16", elems, w["d"])
     step_bytes = sum(KERNEL_PASSES[k] * kernels[k]["launches_per_step"] * elems * 2
                      for k in KERNEL_PASSES if k in kernels)
     del plan, xs
@@ -342,11 +355,18 @@ def main():
             p32.backward()
 
         n32 = max(2, args.steps // 4)
-        t32 = time_steps(step32, n32, 1)
+        step32()
+        torch.cuda.synchronize()
+        la.profile_enable(True)
+        t32 = time_steps(step32, n32, 0)
+        k32 = kernel_table(la.profile_read(), n32, elems, 4)
+        la.profile_enable(False)
         t32f = time_steps(p32.forward, n32, 1)
+        mma32 = mma_flops_per_step(k32, "fp32", elems, w["d"])
         fp32 = {"fwd_bwd_tokens_per_s": round(tokens / t32, 1), "fwd_tokens_per_s": round(tokens / t32f, 1),
                 "ms_per_step": round(t32 * 1e3, 3), "fwd_ms": round(t32f * 1e3, 3),
-                "mma_frac_of_fp32_peak": round(mma_flops / t32 / 1e12 / FP32_PEAK_TFLOPS, 4)}
+                "kernels_ms": {k: v["avg_ms"] for k, v in k32.items()},
+                "mma_frac_of_fp32_peak": round(mma32 / t32 / 1e12 / FP32_PEAK_TFLOPS, 4)}
         log("fp32 fwd+bwd %.3f ms" % (t32 * 1e3))
         del p32, xs
         torch.cuda.empty_cache()
