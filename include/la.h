@@ -73,8 +73,8 @@ enum { LA_PHI_ELU1 = 0 };
  *  out_s* element strides of O, dQ, dK and dV.
  *  Strides must be >= 0, in_sn/out_sn >= d, and every stride times the
  *  element size a multiple of 16 bytes; base pointers 16-byte aligned.
- *  A token stride above 16 MiB (in_sn or out_sn times the element size)
- *  is LA_ERR_UNSUPPORTED.
+ *  A token stride above 16 MiB (in_sn or out_sn times the element size),
+ *  N above 2^36 or B*H above 65535 is LA_ERR_UNSUPPORTED.
  */
 typedef struct {
   int64_t B, H, N, d;

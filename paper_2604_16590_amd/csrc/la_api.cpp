@@ -35,8 +35,10 @@ la_status check_desc(const la_attn_desc* d) {
   if (d->feature_map != LA_PHI_ELU1) return LA_ERR_UNSUPPORTED;
   if (d->flags != 0) return LA_ERR_INVALID_ARG;
   if (d->d != 16 && d->d != 32 && d->d != 64 && d->d != 128) return LA_ERR_UNSUPPORTED;
-  // the grid's y dimension carries (b, h); the token index is 64-bit
-  if (d->B * d->H > 65535 || d->N > (int64_t(1) << 40)) return LA_ERR_UNSUPPORTED;
+  // the grid's y dimension carries (b, h); token indices are 64-bit, but
+  // the tokens of one partial (at most 128 partials per (b, h)) and the
+  // steps over them are counted in 32 bits
+  if (d->B * d->H > 65535 || d->N > (int64_t(1) << 36)) return LA_ERR_UNSUPPORTED;
   const int64_t s[2][3] = {{d->in_sb, d->in_sh, d->in_sn}, {d->out_sb, d->out_sh, d->out_sn}};
   const int es[2] = {elem_size(d->in_dtype), elem_size(d->out_dtype)};
   for (int t = 0; t < 2; ++t) {

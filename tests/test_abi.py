@@ -77,6 +77,16 @@ def test_bad_descriptors_are_rejected(kw, status):
     assert ws_status(desc(**kw))[0] == status
 
 
+def test_size_limits():
+    # N up to 2^36 tokens per (b, h) and up to 65535 (b, h) pairs
+    def big(n):
+        return desc(N=n, in_sb=2 * n * 64, in_sh=n * 64, out_sb=2 * n * 64, out_sh=n * 64)
+    assert ws_status(big(1 << 36))[0] == 0
+    assert ws_status(big((1 << 36) + 1))[0] == 2
+    assert ws_status(desc(B=65535, H=1, in_sb=6400, out_sb=6400))[0] == 0
+    assert ws_status(desc(B=32768, H=2))[0] == 2
+
+
 def test_forward_rejects_bad_pointers_before_gpu_work():
     L = la.lib()
     d = desc()
