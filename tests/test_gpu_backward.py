@@ -216,3 +216,36 @@ def test_long_context_2m_tokens_fwd_bwd_sampled_rows():
     lhs = dv.double().sum(2)
     rhs = xs[3].double().sum(2)
     assert ((lhs - rhs).norm(dim=-1) / rhs.norm(dim=-1)).max().item() < TOL["bf16"]
+
+
+@pytest.mark.parametrize("d", [64, 128])
+def test_beyond_2m_tokens_partials_longer_than_16384(d):
+    # N = 4,194,381 (4 Mi + 77) tokens in one (b, h): the 128 partials each
+    # take ceil(N / 128) rounded up to 64 = 32,832 tokens in fp32, twice the
+    # range of the 2M-token workload, and the last one is ragged.  Exact S, z,
+    # dS, dz from the oracle over all tokens; O, dQ, dK, dV on sampled rows.
+    dev = require_gpu()
+    B, H, N = 1, 1, 4 * 1048576 + 77
+    print("B1 H1 N%d d%d fwd+bwd" % (N, d), flush=True)
+    xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device=dev) for _ in range(4)]
+    for sid, x in enumerate(xs):
+        la.gen_fill(x, seed=1010 + d, stream_id=sid, std=(0.5 ** 0.5 if sid < 3 else 1.0))
+    o, S, z = la.forward(*xs[:3], return_summary=True)
+    dq, dk, dv = la.backward(*xs[:3], S, z, xs[3])
+    torch.cuda.synchronize()
+    hq, hk, hv, hg = (to_host(x) for x in xs)
+    S_ref, z_ref = oracle.summary(hk, hv)
+    assert normwise(S.cpu().numpy(), S_ref) < 4e-3
+    assert normwise(z.cpu().numpy()[..., None], z_ref[..., None]) < 4e-3
+    _, dS_ref, dz_ref = oracle.backward_query(hq, hg, S_ref, z_ref, want_dq=False)
+    rows = np.sort(np.random.default_rng(d).choice(N, 2048, replace=False))
+    rows[-1] = N - 1
+    sel = lambda a: np.ascontiguousarray(a[:, :, rows])
+    o_ref = oracle.apply(sel(hq), S_ref, z_ref)
+    rdq, _, _ = oracle.backward_query(sel(hq), sel(hg), S_ref, z_ref)
+    rdk, rdv = oracle.backward_key(sel(hk), sel(hv), dS_ref, dz_ref)
+    idx = torch.from_numpy(rows).to(dev)
+    for name, x, r in (("o", o, o_ref), ("dq", dq, rdq), ("dk", dk, rdk), ("dv", dv, rdv)):
+        err = normwise(as64(x[:, :, idx]), r)
+        print("N%d d%d" % (N, d), name, err, flush=True)
+        assert err < TOL["bf16"]
