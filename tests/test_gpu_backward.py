@@ -220,10 +220,11 @@ def test_long_context_2m_tokens_fwd_bwd_sampled_rows():
 
 @pytest.mark.parametrize("d", [64, 128])
 def test_beyond_2m_tokens_partials_longer_than_16384(d):
-    # N = 4,194,381 (4 Mi + 77) tokens in one (b, h): the 128 partials each
-    # take ceil(N / 128) rounded up to 64 = 32,832 tokens in fp32, twice the
-    # range of the 2M-token workload, and the last one is ragged.  Exact S, z,
-    # dS, dz from the oracle over all tokens; O, dQ, dK, dV on sampled rows.
+    # N = 4,194,381 (4 Mi + 77) tokens in one (b, h): the partials (128 at
+    # d = 128, 64 below) each take N / P rounded up to 64 tokens in fp32
+    # (32,832 and 65,600), two and four times the range of the 2M-token
+    # workload, and the last one is ragged.  Exact S, z, dS, dz from the
+    # oracle over all tokens; O, dQ, dK, dV on sampled rows.
     dev = require_gpu()
     B, H, N = 1, 1, 4 * 1048576 + 77
     print("B1 H1 N%d d%d fwd+bwd" % (N, d), flush=True)
