@@ -43,6 +43,37 @@ KERNEL_PASSES = {
     "bwd_key": 4,       # read K, V; write dK, dV
 }
 
+# the plain stream with each kernel's read/write mix (the fused query
+# backward reads twice what it writes and matches none of them)
+KERNEL_STREAM = {"summary_fwd": "read", "summary_bwd": "read", "apply": "copy", "bwd_key": "copy"}
+
+
+def stream_ceilings(nbytes, reps=5):
+    """GB/s of the library's plain read, write and copy streams over
+    `nbytes` (a copy counts its reads and its writes), each the mean over
+    `reps` launches timed by the library's kernel timer."""
+    import torch
+    import paper_2604_16590_amd as la
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    la.stream_probe("write", a, pattern=0x3C003C00)
+    la.stream_probe("copy", b, a)
+    torch.cuda.synchronize()
+    la.profile_enable(True)
+    for _ in range(reps):
+        la.stream_probe("read", b, a)
+        la.stream_probe("write", b, pattern=0)
+        la.stream_probe("copy", b, a)
+    stats = la.profile_read()
+    la.profile_enable(False)
+    out = {}
+    for kind, moved in (("read", nbytes), ("write", nbytes), ("copy", 2 * nbytes)):
+        launches, ms = stats["stream_" + kind]
+        out[kind] = round(moved / (ms / launches * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
 
 def kernel_mma(dtype, d):
     """Matrix-core FLOPs per launch of each kernel, in units of 2*B*H*N*d^2.
@@ -337,6 +368,13 @@ def main():
     torch.cuda.empty_cache()
 
     peak_bytes = torch.cuda.max_memory_allocated()
+
+    # ceilings measured the same way: plain streams over one tensor's bytes
+    streams = stream_ceilings(elems * 2)
+    roofline["stream_GB_s"] = streams
+    mix = KERNEL_STREAM.get(dominant)
+    roofline["frac_of_stream"] = {"stream": mix, "frac": round(achieved / streams[mix], 4)} if mix else None
+    log("streams %s" % streams)
 
     # ---- the other workload shapes (context for the same kernels) ----
     others = None

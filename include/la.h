@@ -345,6 +345,26 @@ typedef struct {
 la_status la_profile_enable(int32_t on);
 la_status la_profile_read(la_kernel_stat* out, int32_t capacity, int32_t* count);
 
+/*
+ * Plain HBM streams, the ceilings the attention kernels' rates are read
+ * against: each kernel of the method is bound by HBM traffic with a fixed
+ * mix of reads and writes, and these measure what a kernel of the same mix
+ * reaches on the device (grid-stride loops over 16-byte words).
+ *  kind   LA_STREAM_READ: reads `bytes` of src; dst receives at most 16
+ *         bytes of unspecified content (a sink that keeps the loads live).
+ *         LA_STREAM_WRITE: fills `bytes` of dst with the 32-bit `pattern`
+ *         (src unused, may be NULL).
+ *         LA_STREAM_COPY: copies `bytes` from src to dst (no overlap).
+ *  bytes  > 0, a multiple of 16; device pointers 16-byte aligned, owned by
+ *         the caller.  Violations are LA_ERR_INVALID_ARG, checked before
+ *         anything is enqueued; the call is asynchronous on `stream` and is
+ *         timed by the kernel timer as stream_read / stream_write /
+ *         stream_copy.
+ */
+enum { LA_STREAM_READ = 0, LA_STREAM_WRITE = 1, LA_STREAM_COPY = 2 };
+la_status la_stream_probe(int32_t kind, const void* src, void* dst, size_t bytes,
+                          uint32_t pattern, la_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

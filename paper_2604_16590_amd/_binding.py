@@ -448,3 +448,30 @@ def tiled_attention(q, k, v, core, halo):
     to = torch.empty_like(tq)
     forward(view(tq), view(tk), view(tv), out=view(to))
     return tile_blend(to, (T, Y, X), core, halo).view(T, Y, X, H, d)
+
+
+STREAM_KINDS = {"read": 0, "write": 1, "copy": 2}
+
+
+def stream_probe(kind: str, dst: torch.Tensor, src: torch.Tensor = None, pattern: int = 0):
+    """One plain HBM stream over dst's bytes (read: src's bytes): "read"
+    reads src (dst receives at most 16 bytes), "write" fills dst with the
+    32-bit `pattern`, "copy" copies src into dst.  Contiguous device tensors;
+    runs on torch's current stream."""
+    k = STREAM_KINDS[kind]
+    L = lib()
+    if not getattr(L, "_probe_typed", False):
+        L.la_stream_probe.argtypes = [ctypes.c_int32, VP, VP, ctypes.c_size_t, ctypes.c_uint32, VP]
+        L.la_stream_probe.restype = ctypes.c_int
+        L._probe_typed = True
+    for t in (dst, src):
+        if t is not None and not t.is_contiguous():
+            raise ValueError("stream_probe needs contiguous tensors")
+    nbytes = (src if kind == "read" else dst).numel() * (src if kind == "read" else dst).element_size()
+    if kind == "copy" and src.numel() * src.element_size() != nbytes:
+        raise ValueError("copy: src and dst differ in size")
+    if kind == "read" and dst.numel() * dst.element_size() < 16:
+        raise ValueError("read: dst must hold 16 bytes")
+    _check("la_stream_probe", L.la_stream_probe(k, src.data_ptr() if src is not None else None,
+                                                dst.data_ptr(), nbytes, pattern & 0xFFFFFFFF,
+                                                _stream(dst.device)))

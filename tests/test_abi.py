@@ -168,3 +168,21 @@ def test_tile_geometry_and_validation():
         assert L.la_tile_geometry(ctypes.byref(bad), ctypes.byref(n), ctypes.byref(t)) == 1
     fake = 1 << 20
     assert L.la_tile_extract(ctypes.byref(d), fake + 8, fake, None) == 1
+
+
+def test_stream_probe_rejects_bad_arguments_before_gpu_work():
+    # fake but aligned device addresses: every case is refused before any
+    # HIP call, so nothing is enqueued
+    L = la.lib()
+    L.la_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_uint32, ctypes.c_void_p]
+    L.la_stream_probe.restype = ctypes.c_int
+    a, b = 1 << 20, 1 << 24
+    assert L.la_stream_probe(0, a, b, 0, 0, None) == 1          # no bytes
+    assert L.la_stream_probe(2, a, b, 40, 0, None) == 1         # not a multiple of 16
+    assert L.la_stream_probe(1, None, None, 64, 0, None) == 1   # no destination
+    assert L.la_stream_probe(0, None, b, 64, 0, None) == 1      # read without a source
+    assert L.la_stream_probe(2, a + 8, b, 64, 0, None) == 1     # misaligned source
+    assert L.la_stream_probe(1, None, b + 4, 64, 0, None) == 1  # misaligned destination
+    assert L.la_stream_probe(2, a, a + 16, 64, 0, None) == 1    # overlapping copy
+    assert L.la_stream_probe(3, a, b, 64, 0, None) == 1         # unknown kind
