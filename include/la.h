@@ -99,14 +99,19 @@ la_status la_version(int32_t* major, int32_t* minor);
 
 /*
  * Device workspace the caller must provide for a pass (0 = forward,
- * 1 = backward, 2 = apply), in bytes, 256-byte aligned.  The forward's size depends on
- * (B, H, d, dtype) and on N only through the number of per-tile partial
- * sums, which is capped, so it is bounded independently of N: the state of
- * linear attention per head is O(d^2), whatever the token count.  Where
- * the backward runs its query pass and its dS reduction separately (fp32
- * inputs, and d = 16) it adds 8 bytes per (b, h, token) for the per-query
- * pair (1/den, dden) passed between them; bf16 at d >= 32 runs them as one
- * pass and needs no such buffer.
+ * 1 = backward, 2 = apply), in bytes, 256-byte aligned.  It holds O(d^2)
+ * per head (the FP64 summary and its matrix-core operand images) plus the
+ * per-tile partial sums of the token reduction.  Each partial sums at most
+ * 16,384 tokens (bf16 inputs; 4,096 for fp32) in FP32 before the partials
+ * are added in FP64, so the FP32 part of every sum over tokens is bounded
+ * whatever N is; the partial count is 128 (d = 128) or 64 (d < 128) until
+ * that bound is reached (2,097,152 or 1,048,576 bf16 tokens per head) and
+ * grows with N beyond it, by (d*d + d) * 4 bytes per 16,384 tokens per
+ * head (0.8 % of the bytes of K and V at d = 128).  Where the backward runs
+ * its query pass and its dS reduction separately (fp32 inputs, and
+ * d = 16) it adds 8 bytes per (b, h, token) for the per-query pair
+ * (1/den, dden) passed between them; bf16 at d >= 32 runs them as one pass
+ * and needs no such buffer.
  */
 la_status la_workspace_size(const la_attn_desc* desc, int32_t pass, size_t* bytes);
 
@@ -282,6 +287,22 @@ typedef struct {
   uint64_t gen_seed;
   double gen_std;
   uint64_t t_arrival_ns; /* scheduled arrival on CLOCK_MONOTONIC; 0 = at submit */
+  uint64_t reuse_summary_of; /* 0: compute S, z of this request's keys and
+                            values (the forward).  Otherwise the id of an
+                            earlier, not yet released request of this server
+                            with the same B, H, d and in_dtype (N may differ):
+                            this request applies its own queries against that
+                            request's S and z (la_apply) -- the per-step work
+                            of temporal cross-attention against a fixed
+                            history (Sec. III-B) over an ensemble member's
+                            diffusion steps (Sec. V).  k and v must be NULL;
+                            with generate = 1 only Q is generated (stream 0 of
+                            gen_seed).  It starts once that request is DONE
+                            and FAILs with its error if it FAILED; while it is
+                            pending, releasing that request returns
+                            LA_ERR_BUSY.  Errors at submit: LA_ERR_NOT_FOUND
+                            (unknown id), LA_ERR_INVALID_ARG (a request that
+                            itself reuses, one that FAILED, or a mismatch). */
 } la_request;
 
 enum { LA_REQ_QUEUED = 0, LA_REQ_RUNNING = 1, LA_REQ_DONE = 2, LA_REQ_FAILED = 3 };
@@ -292,8 +313,9 @@ typedef struct {
   uint64_t t_arrival_ns, t_admit_ns, t_done_ns;  /* CLOCK_MONOTONIC */
   int32_t slices;         /* member slices the request was split into */
   void* o;                /* output (server-owned for generated requests) */
-  double* s;              /* [B][H][d][d] FP64 summary, server-owned */
-  double* z;              /* [B][H][d]    FP64 normaliser, server-owned */
+  double* s;              /* [B][H][d][d] FP64 summary, server-owned (NULL
+                             for a request that reuses another's) */
+  double* z;              /* [B][H][d]    FP64 normaliser, server-owned (idem) */
   double gen_ms;          /* device time generating inputs, summed over slices */
   double attn_ms;         /* device time of the attention, summed over slices */
 } la_result;
@@ -316,12 +338,18 @@ la_status la_serve_submit(la_server* srv, const la_request* req, uint64_t* id);
 /* Non-blocking snapshot.  LA_ERR_NOT_FOUND for unknown or released ids. */
 la_status la_serve_poll(la_server* srv, uint64_t id, la_result* out);
 /* Free a finished request's device memory (S, z, generated O).
- * LA_ERR_BUSY while it is queued or running. */
+ * LA_ERR_BUSY while it is queued or running, or while requests reusing its
+ * summary are pending. */
 la_status la_serve_release(la_server* srv, uint64_t id);
 la_status la_serve_stats(la_server* srv, la_serve_counters* out);
 /* Test hook: slice `slice` (0-based) of request `id` fails instead of
  * running, as a device-side failure would. */
 la_status la_serve_debug_fail_slice(la_server* srv, uint64_t id, int32_t slice);
+/* Test hook: slice `slice` of request `id` fails after its inputs are on
+ * its stream (generated, or its start recorded), before the attention, as
+ * a launch failing midway would; its memory stays held until the work
+ * already enqueued has drained. */
+la_status la_serve_debug_fail_slice_late(la_server* srv, uint64_t id, int32_t slice);
 /* Test hook: while paused (1) the scheduler admits nothing; slices already
  * in flight still finish.  0 resumes. */
 la_status la_serve_debug_pause(la_server* srv, int32_t paused);

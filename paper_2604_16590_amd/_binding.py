@@ -115,6 +115,16 @@ def _strides(x: torch.Tensor):
     return x.stride(0), x.stride(1), x.stride(2)
 
 
+def _dense(x: torch.Tensor) -> bool:
+    """True if x's elements occupy distinct, gap-free storage (any order)."""
+    expect = 1
+    for st, n in sorted((st, n) for st, n in zip(x.stride(), x.shape) if n > 1):
+        if st != expect:
+            return False
+        expect *= n
+    return True
+
+
 def make_desc(q: torch.Tensor, out: torch.Tensor) -> AttnDesc:
     B, H, N, d = q.shape
     isb, ish, isn = _strides(q)
@@ -304,9 +314,19 @@ class LinearAttention(torch.autograd.Function):
     @staticmethod
     def backward(ctx, do):
         q, k, v, S, z = ctx.saved_tensors
-        if do.dtype != q.dtype or _strides(do) != _strides(q):
-            buf = torch.empty_strided(q.shape, q.stride(), dtype=q.dtype, device=q.device)
-            do = buf.copy_(do)
+        # The kernels read dO with q's dtype and strides.  Autograd may hand
+        # over any layout (the gradient of o.sum() is an expanded tensor with
+        # all strides 0, a transposed gradient has a non-unit feature
+        # stride): compare the raw strides and copy into q's layout when they
+        # differ, or into a dense layout for all four when q's own layout
+        # overlaps itself (a broadcast q).
+        if do.dtype != q.dtype or do.stride() != q.stride():
+            if _dense(q):
+                buf = torch.empty_strided(q.shape, q.stride(), dtype=q.dtype, device=q.device)
+                do = buf.copy_(do)
+            else:
+                q, k, v = (t.contiguous() for t in (q, k, v))
+                do = do.to(q.dtype).contiguous()
         return backward(q, k, v, S, z, do)
 
 

@@ -35,9 +35,9 @@ la_status check_desc(const la_attn_desc* d) {
   if (d->feature_map != LA_PHI_ELU1) return LA_ERR_UNSUPPORTED;
   if (d->flags != 0) return LA_ERR_INVALID_ARG;
   if (d->d != 16 && d->d != 32 && d->d != 64 && d->d != 128) return LA_ERR_UNSUPPORTED;
-  // the grid's y dimension carries (b, h); token indices are 64-bit, but
-  // the tokens of one partial (at least N / 128 of them) and the
-  // steps over them are counted in 32 bits
+  // the grid's y dimension carries (b, h); token indices are 64-bit, while
+  // partials (N / 4096 at most) and workgroups along x (N / 2048 at most)
+  // are counted in 32 bits
   if (d->B * d->H > 65535 || d->N > (int64_t(1) << 36)) return LA_ERR_UNSUPPORTED;
   const int64_t s[2][3] = {{d->in_sb, d->in_sh, d->in_sn}, {d->out_sb, d->out_sh, d->out_sn}};
   const int es[2] = {elem_size(d->in_dtype), elem_size(d->out_dtype)};
@@ -57,20 +57,31 @@ la_status check_desc(const la_attn_desc* d) {
 // gives bitwise the same result whatever batch it is part of.
 struct Tiling {
   int P;   // partial sums per (b, h)
-  int Tw;  // tokens per partial (a multiple of 32)
+  int Tw;  // tokens per partial (a multiple of 64, at most max_fp32_run)
   int Ta;  // tokens per apply workgroup
   int Tk;  // tokens per workgroup of the key (and two-pass query) backward
 };
 
-Tiling choose_tiling(int64_t N, int d) {
+// The longest token range any kernel sums in FP32: each partial sum covers
+// at most this many tokens, and partials are added in FP64 (the combine),
+// so the FP32 part of every sum over tokens is bounded whatever N is.
+// The fp32 path, which is held to a tighter tolerance, takes shorter runs.
+int64_t max_fp32_run(int dt) { return dt == LA_BF16 ? 16384 : 4096; }
+
+Tiling choose_tiling(int64_t N, int d, int dt) {
   const int64_t tw_min = d >= 128 ? 2048 : 1024;
-  // at most 128 partials at d = 128 and 64 below: longer ranges per wave
-  // paid off at d = 64 (summary of 32 heads x 262,144 tokens 0.38 -> 0.33
-  // ms), while 8 heads at d = 128 need the 128 to give each SIMD a wave
+  // at most 128 partials at d = 128 and 64 below while that keeps each
+  // FP32 run within max_fp32_run: longer ranges per wave paid off at d = 64
+  // (summary of 32 heads x 262,144 tokens 0.38 -> 0.33 ms), while 8 heads
+  // at d = 128 need the 128 to give each SIMD a wave.  Beyond that the
+  // partial count grows with N (about (d^2 + d) * 4 bytes of workspace per
+  // max_fp32_run tokens per head: 0.8 % of the inputs' bytes at d = 128).
   const int64_t p_max = d >= 128 ? 128 : 64;
   int64_t P = std::min<int64_t>(p_max, ceil_div(N, tw_min));
+  P = std::max<int64_t>(P, ceil_div(N, max_fp32_run(dt)));
   // a multiple of 64: the summary steps over 32 tokens, the fused
-  // backward over 64 (four waves x 16)
+  // backward over 64 (four waves x 16); max_fp32_run is one too, so
+  // rounding up keeps Tw <= max_fp32_run
   int64_t Tw = ceil_div(ceil_div(N, P), 64) * 64;
   P = ceil_div(N, Tw);
   Tiling t;
@@ -108,7 +119,7 @@ bool fused_backward(const la_attn_desc* d) { return d->in_dtype == LA_BF16 && d-
 
 Layout layout_for(const la_attn_desc* d, int pass) {
   const int64_t BH = d->B * d->H, D = d->d;
-  const Tiling t = choose_tiling(d->N, (int)D);
+  const Tiling t = choose_tiling(d->N, (int)D, d->in_dtype);
   const size_t part = align_up((size_t)BH * t.P * (D * D + D) * sizeof(float));
   const size_t mat = align_up((size_t)BH * D * D * sizeof(double));
   const size_t vec = align_up((size_t)BH * D * sizeof(double));
@@ -155,7 +166,7 @@ la_status forward_impl(const la_attn_desc* desc, const void* q, const void* k, c
   if (((uintptr_t)s_out & 7u) || ((uintptr_t)z_out & 7u)) return LA_ERR_INVALID_ARG;
   const Layout L = layout_for(desc, 0);
   if (ws_bytes < L.total) return LA_ERR_OOM;
-  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  const Tiling t = choose_tiling(desc->N, (int)desc->d, desc->in_dtype);
   char* w = (char*)ws;
   la::FwdArgs a{};
   a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
@@ -186,7 +197,7 @@ la_status apply_impl(const la_attn_desc* desc, const void* q, const double* s, c
   if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
   const Layout L = layout_for(desc, 2);
   if (ws_bytes < L.total) return LA_ERR_OOM;
-  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  const Tiling t = choose_tiling(desc->N, (int)desc->d, desc->in_dtype);
   la::FwdArgs a{};
   a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;
   a.in_dt = desc->in_dtype; a.out_dt = desc->out_dtype;
@@ -282,7 +293,7 @@ la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,
   if (((uintptr_t)ws % kAlign) != 0) return LA_ERR_INVALID_ARG;
   const Layout L = layout_for(desc, 1);
   if (ws_bytes < L.total) return LA_ERR_OOM;
-  const Tiling t = choose_tiling(desc->N, (int)desc->d);
+  const Tiling t = choose_tiling(desc->N, (int)desc->d, desc->in_dtype);
   char* w = (char*)ws;
   la::BwdArgs a{};
   a.B = desc->B; a.H = desc->H; a.N = desc->N; a.D = (int)desc->d;

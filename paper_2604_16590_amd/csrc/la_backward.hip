@@ -460,9 +460,13 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
   for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
 
   prefetch(t_begin);
+  // the first step's inputs (no stores are in flight yet)
+  wait_vmem<0>();
   for (int64_t t0 = t_begin; t0 < t_end; t0 += 16 * TT) {
-    // this step's runs: wait for its prefetch (the previous step's dQ
-    // stores may still be in flight), read them, then refill the stage
+    // this step's runs: wait for its prefetch, issued before the previous
+    // step's NSTORE dQ stores (the counter retires in issue order, so at
+    // most NSTORE outstanding means the prefetch has landed), read them,
+    // then refill the stage
     wait_vmem<FC::NSTORE>();
     uint32_t pq[TT][RW], pg[TT][RW];
 #pragma unroll

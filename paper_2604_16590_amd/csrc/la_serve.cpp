@@ -10,7 +10,18 @@
 // run as memory frees up while other requests' slices overlap on the
 // device.  The budget is one device allocation carved by a first-fit
 // allocator, so admission never calls hipMalloc.
-#include <hip/hip_runtime.h>
+//
+// Summary reuse: a request may name an earlier request whose FP64 summary
+// S and normaliser z the server still holds; it then runs the apply only
+// (la_apply of its own queries against them), the per-step work of the
+// paper's temporal cross-attention against a fixed compressed history
+// (Sec. III-B) over the diffusion steps of an ensemble member (Sec. V).
+// It starts once that request is DONE, and that request cannot be released
+// while requests reusing it are pending.
+//
+// Only the HIP runtime API is used here (no device code), so the file also
+// builds as plain host C++ for the thread-sanitizer run of the scheduler.
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <chrono>
@@ -26,7 +37,6 @@
 
 #include "../../include/la.h"
 #include "../../include/la_gen.h"
-#include "la_kernels.h"
 
 namespace {
 
@@ -102,7 +112,10 @@ struct Slice {
   int stream;
   hipEvent_t start, gen, done;  // timed events: slice start, inputs ready, done
   uint64_t t_fake_done;
-  bool fail;
+  bool fail;           // test hook: fails before anything is enqueued
+  bool fail_late;      // test hook: fails after its inputs are enqueued
+  bool failed_launch;  // its launch failed after work was enqueued: it is
+                       // retired (as failed) only once that work drained
 };
 
 struct Request {
@@ -117,9 +130,12 @@ struct Request {
   double gen_ms = 0.0, attn_ms = 0.0;    // device time summed over slices
   bool keep_held = false;
   void* o = nullptr;
-  double* s = nullptr;
+  double* s = nullptr;  // this request's S, z (the owner's when reusing)
   double* z = nullptr;
+  int reusers = 0;      // pending requests that apply this one's S, z
 };
+
+bool reuses(const la_request& r) { return r.reuse_summary_of != 0; }
 
 int64_t esize(int32_t dt) { return dt == LA_BF16 ? 2 : 4; }
 
@@ -140,7 +156,7 @@ struct la_server {
   std::deque<uint64_t> fifo;
   std::unordered_map<uint64_t, Request> reqs;
   std::vector<Slice> inflight;
-  std::set<std::pair<uint64_t, int>> fail_at;
+  std::set<std::pair<uint64_t, int>> fail_at, fail_late_at;
   std::thread th;
   bool stopping = false;
   bool paused = false;
@@ -151,8 +167,9 @@ struct la_server {
 
 namespace {
 
-// Transient bytes of a slice of m members: generated Q, K, V plus the
-// forward workspace.  Kept bytes of a request: S, z and a generated O.
+// Transient bytes of a slice of m members: generated inputs (Q, K, V; Q
+// only when reusing a summary) plus the workspace of the forward (apply).
+// Kept bytes of a request: S, z (not when reusing) and a generated O.
 size_t slice_bytes(const la_request& r, int64_t m) {
   la_attn_desc d = r.desc;
   d.B = m;
@@ -161,17 +178,33 @@ size_t slice_bytes(const la_request& r, int64_t m) {
     d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh; d.out_sn = d.d;
   }
   size_t ws = 0;
-  la_workspace_size(&d, 0, &ws);
+  la_workspace_size(&d, reuses(r) ? 2 : 0, &ws);
   size_t b = align_up(ws);
-  if (r.generate) b += 3 * align_up(member_tensor_bytes(d, d.in_dtype) * (size_t)m);
+  const size_t n_gen = reuses(r) ? 1 : 3;
+  if (r.generate) b += n_gen * align_up(member_tensor_bytes(d, d.in_dtype) * (size_t)m);
   return b;
 }
 
 size_t keep_bytes(const la_request& r) {
   const la_attn_desc& d = r.desc;
-  size_t b = align_up((size_t)(d.B * d.H * d.d * d.d) * 8) + align_up((size_t)(d.B * d.H * d.d) * 8);
+  size_t b = 0;
+  if (!reuses(r))
+    b += align_up((size_t)(d.B * d.H * d.d * d.d) * 8) + align_up((size_t)(d.B * d.H * d.d) * 8);
   if (r.generate) b += align_up(member_tensor_bytes(d, d.out_dtype) * (size_t)d.B);
-  return b;
+  return std::max<size_t>(b, 1);
+}
+
+// A request reaches DONE or FAILED: stamps, counters, and the owner of a
+// reused summary has one pending reuser less.
+void complete_request(la_server* s, Request& rq, bool failed, la_status err) {
+  rq.t_done = now_ns();
+  rq.state = failed ? LA_REQ_FAILED : LA_REQ_DONE;
+  if (failed) rq.error = err;
+  if (failed) s->n_failed += 1; else s->n_completed += 1;
+  if (reuses(rq.spec)) {
+    auto ot = s->reqs.find(rq.spec.reuse_summary_of);
+    if (ot != s->reqs.end()) ot->second.reusers -= 1;
+  }
 }
 
 hipEvent_t take_event(la_server* s) {
@@ -186,11 +219,18 @@ hipEvent_t take_event(la_server* s) {
   return e;
 }
 
-// Enqueue one slice on its stream (called with the lock held).
-la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
+// Enqueue one slice on its stream (called with the lock held).  On
+// failure *enqueued tells whether work was already put on the stream (it
+// may still write the slice's memory).
+la_status launch_slice(la_server* s, Request& rq, Slice& sl, bool* enqueued) {
+  *enqueued = false;
   if (sl.fail) return LA_ERR_HIP;  // injected device failure
   if (s->cfg.fake_executor) {
     sl.t_fake_done = now_ns() + (uint64_t)s->cfg.fake_slice_ns;
+    if (sl.fail_late) {  // its (simulated) inputs are on the way
+      *enqueued = true;
+      return LA_ERR_HIP;
+    }
     return LA_OK;
   }
   const la_request& r = rq.spec;
@@ -201,6 +241,8 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
   const void *q, *k, *v;
   void* o;
   if (hipEventRecord(sl.start, st) != hipSuccess) return LA_ERR_HIP;
+  *enqueued = true;
+  const int n_gen = reuses(r) ? 1 : 3;
   if (r.generate) {
     d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh; d.in_sn = d.d;
     d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh; d.out_sn = d.d;
@@ -209,7 +251,7 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
     char* gk = blk + tb;
     char* gv = blk + 2 * tb;
     char* bufs[3] = {gq, gk, gv};
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < n_gen; ++t) {
       la_gen_spec g{};
       g.seed = r.gen_seed;
       g.stream = (uint32_t)t;
@@ -223,7 +265,7 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
     }
     q = gq; k = gk; v = gv;
     o = (char*)rq.o + (size_t)sl.b0 * member_tensor_bytes(d, d.out_dtype);
-    blk += 3 * tb;
+    blk += n_gen * tb;
   } else {
     const int64_t ie = esize(d.in_dtype), oe = esize(d.out_dtype);
     q = (const char*)r.q + sl.b0 * d.in_sb * ie;
@@ -231,12 +273,14 @@ la_status launch_slice(la_server* s, Request& rq, Slice& sl) {
     v = (const char*)r.v + sl.b0 * d.in_sb * ie;
     o = (char*)r.o + sl.b0 * d.out_sb * oe;
   }
+  if (sl.fail_late) return LA_ERR_HIP;  // injected failure after the inputs
   if (hipEventRecord(sl.gen, st) != hipSuccess) return LA_ERR_HIP;
   size_t ws = 0;
-  la_workspace_size(&d, 0, &ws);
+  la_workspace_size(&d, reuses(r) ? 2 : 0, &ws);
   double* S = rq.s + (size_t)sl.b0 * d.H * d.d * d.d;
   double* z = rq.z + (size_t)sl.b0 * d.H * d.d;
-  la_status st2 = la_forward(&d, q, k, v, o, S, z, blk, ws, st);
+  const la_status st2 = reuses(r) ? la_apply(&d, q, S, z, o, blk, ws, st)
+                                  : la_forward(&d, q, k, v, o, S, z, blk, ws, st);
   if (st2 != LA_OK) return st2;
   if (hipEventRecord(sl.done, st) != hipSuccess) return LA_ERR_HIP;
   return LA_OK;
@@ -263,11 +307,8 @@ void finish_slice(la_server* s, Slice& sl, bool ok) {
     rq.error = LA_ERR_HIP;
   }
   const bool all_admitted = rq.next_member >= rq.spec.desc.B;
-  if (all_admitted && rq.slices_done == rq.slices_started) {
-    rq.t_done = now_ns();
-    rq.state = rq.failed ? LA_REQ_FAILED : LA_REQ_DONE;
-    if (rq.failed) s->n_failed += 1; else s->n_completed += 1;
-  }
+  if (all_admitted && rq.slices_done == rq.slices_started)
+    complete_request(s, rq, rq.failed, rq.error);
 }
 
 // Retire finished slices; returns how many finished.
@@ -285,7 +326,7 @@ int retire(la_server* s) {
       else if (e != hipErrorNotReady) { done = true; ok = false; }
     }
     if (done) {
-      finish_slice(s, sl, ok);
+      finish_slice(s, sl, ok && !sl.failed_launch);
       s->inflight[i] = s->inflight.back();
       s->inflight.pop_back();
       ++n;
@@ -312,6 +353,23 @@ int admit(la_server* s) {
     Request& rq = it->second;
     if (cap > 0 && rq.slices_started - rq.slices_done >= cap) { ++fit; continue; }
     const la_request& r = rq.spec;
+    if (reuses(r)) {
+      // the owner cannot be released while this request is pending
+      const Request& ow = s->reqs.at(r.reuse_summary_of);
+      if (ow.state == LA_REQ_FAILED) {  // nothing to apply: fail, nothing started
+        rq.next_member = r.desc.B;
+        complete_request(s, rq, true, ow.error);
+        fit = s->fifo.erase(fit);
+        ++n;
+        continue;
+      }
+      if (ow.state != LA_REQ_DONE) {  // its summary is not complete yet
+        if (cap > 0) { ++fit; continue; }
+        break;
+      }
+      rq.s = ow.s;
+      rq.z = ow.z;
+    }
     if (!rq.keep_held) {
       size_t off;
       if (!s->arena.alloc(keep_bytes(r), &off)) break;
@@ -320,12 +378,14 @@ int admit(la_server* s) {
       rq.keep_bytes = keep_bytes(r);
       char* p = s->base ? s->base + off : nullptr;
       const la_attn_desc& d = r.desc;
-      rq.s = (double*)p;
-      rq.z = (double*)(p ? p + align_up((size_t)(d.B * d.H * d.d * d.d) * 8) : nullptr);
+      const size_t sz = reuses(r) ? 0 : align_up((size_t)(d.B * d.H * d.d * d.d) * 8) +
+                                            align_up((size_t)(d.B * d.H * d.d) * 8);
+      if (!reuses(r)) {
+        rq.s = (double*)p;
+        rq.z = (double*)(p ? p + align_up((size_t)(d.B * d.H * d.d * d.d) * 8) : nullptr);
+      }
       if (r.generate)
-        rq.o = p ? p + align_up((size_t)(d.B * d.H * d.d * d.d) * 8) +
-                       align_up((size_t)(d.B * d.H * d.d) * 8)
-                 : nullptr;
+        rq.o = p ? p + sz : nullptr;
       else
         rq.o = r.o;
     }
@@ -354,6 +414,7 @@ int admit(la_server* s) {
     sl.gen = take_event(s);
     sl.done = take_event(s);
     sl.fail = s->fail_at.count({id, sl.index}) > 0;
+    sl.fail_late = s->fail_late_at.count({id, sl.index}) > 0;
     if (!s->cfg.fake_executor && !(sl.start && sl.gen && sl.done)) {
       for (hipEvent_t e : {sl.start, sl.gen, sl.done})
         if (e) s->events.push_back(e);
@@ -367,10 +428,27 @@ int admit(la_server* s) {
     rq.next_member += m;
     rq.slices_started += 1;
     const bool all_admitted = rq.next_member >= r.desc.B;
-    const la_status st = launch_slice(s, rq, sl);
-    if (st != LA_OK) {
+    bool enqueued = false;
+    const la_status st = launch_slice(s, rq, sl, &enqueued);
+    if (st == LA_OK) {
+      s->inflight.push_back(sl);
+    } else if (!enqueued) {
       finish_slice(s, sl, false);
     } else {
+      // Work already on the slice's stream may still write its memory:
+      // keep the block until that work has drained (a marker event behind
+      // it; without one, wait here), then retire the slice as failed.
+      sl.failed_launch = true;
+      if (!s->cfg.fake_executor) {
+        hipStream_t stm = s->streams[sl.stream];
+        if (hipEventRecord(sl.done, stm) != hipSuccess) {
+          (void)hipStreamSynchronize(stm);
+          finish_slice(s, sl, false);
+          if (all_admitted) fit = s->fifo.erase(fit);
+          ++n;
+          continue;
+        }
+      }
       s->inflight.push_back(sl);
     }
     if (all_admitted) fit = s->fifo.erase(fit);
@@ -445,10 +523,7 @@ la_status la_serve_destroy(la_server* s) {
       Request& rq = it->second;
       rq.next_member = rq.spec.desc.B;
       if (rq.slices_started == rq.slices_done) {
-        rq.state = LA_REQ_FAILED;
-        rq.error = LA_ERR_SHUTDOWN;
-        rq.t_done = now_ns();
-        s->n_failed += 1;
+        complete_request(s, rq, true, LA_ERR_SHUTDOWN);
       } else {
         rq.failed = true;
         rq.error = LA_ERR_SHUTDOWN;
@@ -471,24 +546,39 @@ la_status la_serve_submit(la_server* s, const la_request* r, uint64_t* id) {
   if (!s || !r || !id) return LA_ERR_INVALID_ARG;
   la_request req = *r;
   la_attn_desc& d = req.desc;
+  const bool reuse = reuses(req);
   if (req.generate) {
     if (r->q || r->k || r->v || r->o) return LA_ERR_INVALID_ARG;
     if (!(req.gen_std > 0.0)) return LA_ERR_INVALID_ARG;
     d.in_sn = d.d; d.in_sh = d.N * d.d; d.in_sb = d.H * d.in_sh;
     d.out_sn = d.d; d.out_sh = d.N * d.d; d.out_sb = d.H * d.out_sh;
+  } else if (reuse) {
+    if (r->k || r->v) return LA_ERR_INVALID_ARG;  // the owner's summary stands for them
+    if (!s->cfg.fake_executor && (!r->q || !r->o)) return LA_ERR_INVALID_ARG;
   } else if (!s->cfg.fake_executor && (!r->q || !r->k || !r->v || !r->o)) {
     return LA_ERR_INVALID_ARG;
   }
   size_t ws = 0;
-  la_status st = la_workspace_size(&d, 0, &ws);
+  la_status st = la_workspace_size(&d, reuse ? 2 : 0, &ws);
   if (st != LA_OK) return st;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return LA_ERR_SHUTDOWN;
+  Request* owner = nullptr;
+  if (reuse) {
+    auto ot = s->reqs.find(req.reuse_summary_of);
+    if (ot == s->reqs.end()) return LA_ERR_NOT_FOUND;
+    owner = &ot->second;
+    const la_attn_desc& od = owner->spec.desc;
+    if (reuses(owner->spec) || owner->state == LA_REQ_FAILED || od.B != d.B || od.H != d.H ||
+        od.d != d.d || od.in_dtype != d.in_dtype)
+      return LA_ERR_INVALID_ARG;
+  }
   if (keep_bytes(req) + slice_bytes(req, 1) > s->arena.size()) {
     s->n_rejected += 1;
     return LA_ERR_OOM;
   }
   const uint64_t rid = s->next_id++;
+  if (owner) owner->reusers += 1;
   Request rq;
   rq.spec = req;
   rq.t_arrival = req.t_arrival_ns ? req.t_arrival_ns : now_ns();
@@ -514,8 +604,9 @@ la_status la_serve_poll(la_server* s, uint64_t id, la_result* out) {
   r.t_done_ns = rq.t_done;
   r.slices = rq.slices_started;
   r.o = rq.o;
-  r.s = rq.s;
-  r.z = rq.z;
+  // a reusing request reports no S, z of its own (its owner's stay with it)
+  r.s = reuses(rq.spec) ? nullptr : rq.s;
+  r.z = reuses(rq.spec) ? nullptr : rq.z;
   r.gen_ms = rq.gen_ms;
   r.attn_ms = rq.attn_ms;
   *out = r;
@@ -529,6 +620,7 @@ la_status la_serve_release(la_server* s, uint64_t id) {
   if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
   Request& rq = it->second;
   if (rq.state != LA_REQ_DONE && rq.state != LA_REQ_FAILED) return LA_ERR_BUSY;
+  if (rq.reusers > 0) return LA_ERR_BUSY;  // its S, z are still to be applied
   if (rq.keep_held) s->arena.release(rq.keep_off, rq.keep_bytes);
   s->reqs.erase(it);
   s->cv.notify_all();
@@ -559,6 +651,16 @@ la_status la_serve_debug_fail_slice(la_server* s, uint64_t id, int32_t slice) {
   if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
   if (it->second.slices_started > slice) return LA_ERR_BUSY;  // already launched
   s->fail_at.insert({id, slice});
+  return LA_OK;
+}
+
+la_status la_serve_debug_fail_slice_late(la_server* s, uint64_t id, int32_t slice) {
+  if (!s || slice < 0) return LA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return LA_ERR_NOT_FOUND;
+  if (it->second.slices_started > slice) return LA_ERR_BUSY;  // already launched
+  s->fail_late_at.insert({id, slice});
   return LA_OK;
 }
 

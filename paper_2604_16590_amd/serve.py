@@ -25,7 +25,7 @@ class Request(ctypes.Structure):
     _fields_ = [("desc", B.AttnDesc), ("q", ctypes.c_void_p), ("k", ctypes.c_void_p),
                 ("v", ctypes.c_void_p), ("o", ctypes.c_void_p), ("generate", ctypes.c_int32),
                 ("gen_seed", ctypes.c_uint64), ("gen_std", ctypes.c_double),
-                ("t_arrival_ns", ctypes.c_uint64)]
+                ("t_arrival_ns", ctypes.c_uint64), ("reuse_summary_of", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -55,10 +55,12 @@ def _lib():
         L.la_serve_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.la_serve_stats.argtypes = [ctypes.c_void_p, P(Counters)]
         L.la_serve_debug_fail_slice.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
+        L.la_serve_debug_fail_slice_late.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
+                                                     ctypes.c_int32]
         L.la_serve_debug_pause.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         for n in ("la_serve_create", "la_serve_destroy", "la_serve_submit", "la_serve_poll",
                   "la_serve_release", "la_serve_stats", "la_serve_debug_fail_slice",
-                  "la_serve_debug_pause"):
+                  "la_serve_debug_fail_slice_late", "la_serve_debug_pause"):
             getattr(L, n).restype = ctypes.c_int
         L._serve_typed = True
     return L
@@ -93,12 +95,15 @@ class Server:
         self.close()
 
     def submit(self, desc, q=None, k=None, v=None, o=None, gen_seed=None, gen_std=1.0,
-               t_arrival_ns=0):
+               t_arrival_ns=0, reuse_summary_of=0):
         """Submit one request; tensors are device tensors (kept alive by the
-        caller) or None with gen_seed for server-generated inputs."""
+        caller) or None with gen_seed for server-generated inputs.  With
+        reuse_summary_of = an earlier request's id, only the queries are
+        given (or generated) and applied against that request's S, z."""
         ptr = lambda t: None if t is None else (t if isinstance(t, int) else t.data_ptr())
         req = Request(desc, ptr(q), ptr(k), ptr(v), ptr(o), 1 if gen_seed is not None else 0,
-                      int(gen_seed or 0), float(gen_std), int(t_arrival_ns))
+                      int(gen_seed or 0), float(gen_std), int(t_arrival_ns),
+                      int(reuse_summary_of))
         rid = ctypes.c_uint64(0)
         B._check("la_serve_submit", _lib().la_serve_submit(self.h, ctypes.byref(req), ctypes.byref(rid)))
         return rid.value
@@ -129,8 +134,15 @@ class Server:
     def pause(self, paused=True):
         B._check("la_serve_debug_pause", _lib().la_serve_debug_pause(self.h, 1 if paused else 0))
 
-    def fail_slice(self, rid, slice_index):
-        B._check("la_serve_debug_fail_slice", _lib().la_serve_debug_fail_slice(self.h, rid, slice_index))
+    def fail_slice(self, rid, slice_index, late=False):
+        """Test hook: the slice fails before anything is enqueued, or (late)
+        after its inputs are on its stream."""
+        if late:
+            B._check("la_serve_debug_fail_slice_late",
+                     _lib().la_serve_debug_fail_slice_late(self.h, rid, slice_index))
+        else:
+            B._check("la_serve_debug_fail_slice",
+                     _lib().la_serve_debug_fail_slice(self.h, rid, slice_index))
 
 
 def percentile(xs, p):

@@ -54,12 +54,25 @@ def test_status_strings():
     assert L.la_status_string(99) == b"LA_ERR_UNKNOWN"
 
 
-def test_workspace_size_valid_and_bounded_in_N():
-    st, small = ws_status(desc(N=1 << 16))
-    assert st == 0 and small > 0
-    st, big = ws_status(desc(N=1 << 30, in_sb=2 * (1 << 30) * 64, in_sh=(1 << 30) * 64,
-                             out_sb=2 * (1 << 30) * 64, out_sh=(1 << 30) * 64))
-    assert st == 0 and big <= 2 * small  # capped number of partial sums
+def test_workspace_size_valid_and_grows_only_with_partials():
+    # B2 H1 d64 bf16: 64 partial sums per head up to 64 x 16,384 tokens,
+    # then one more per 16,384 tokens (no FP32 sum covers more), each
+    # (d^2 + d) FP32 values; everything else is O(d^2) per head
+    def ws(n):
+        st, nbytes = ws_status(desc(N=n, in_sb=2 * n * 64, in_sh=n * 64,
+                                    out_sb=2 * n * 64, out_sh=n * 64))
+        assert st == 0 and nbytes > 0
+        return nbytes
+    part = 2 * (64 * 64 + 64) * 4
+    small = ws(1 << 16)
+    assert ws(64 * 16384) == small                      # still 64 partials
+    for n in (64 * 16384 + 1, 1 << 30, (1 << 30) + 77):
+        P = -(-n // 16384)
+        assert abs(ws(n) - (small + (P - 64) * part)) <= 512, n
+    # fp32 inputs: at most 4,096 tokens per partial
+    st, f = ws_status(desc(N=1 << 20, in_dtype=1, out_dtype=1, in_sb=2 * (1 << 20) * 64,
+                           in_sh=(1 << 20) * 64, out_sb=2 * (1 << 20) * 64, out_sh=(1 << 20) * 64))
+    assert st == 0 and f >= 2 * 256 * (64 * 64 + 64) * 4
     assert ws_status(desc(), 1)[0] == 0
     assert ws_status(desc(), 2)[0] == 0
     assert ws_status(desc(), 3)[0] == 1

@@ -219,12 +219,12 @@ def test_long_context_2m_tokens_fwd_bwd_sampled_rows():
 
 
 @pytest.mark.parametrize("d", [64, 128])
-def test_beyond_2m_tokens_partials_longer_than_16384(d):
-    # N = 4,194,381 (4 Mi + 77) tokens in one (b, h): the partials (128 at
-    # d = 128, 64 below) each take N / P rounded up to 64 tokens in fp32
-    # (32,832 and 65,600), two and four times the range of the 2M-token
-    # workload, and the last one is ragged.  Exact S, z, dS, dz from the
-    # oracle over all tokens; O, dQ, dK, dV on sampled rows.
+def test_beyond_2m_tokens_partial_count_grows(d):
+    # N = 4,194,381 (4 Mi + 77) tokens in one (b, h): past the point where
+    # 128 (d = 128) or 64 (d = 64) partials would each sum more than 16,384
+    # tokens in FP32, so the partial count grows instead (257 partials of
+    # 16,384 tokens, the last one 77 tokens long).  Exact S, z, dS, dz from
+    # the oracle over all tokens; O, dQ, dK, dV on sampled rows.
     dev = require_gpu()
     B, H, N = 1, 1, 4 * 1048576 + 77
     print("B1 H1 N%d d%d fwd+bwd" % (N, d), flush=True)
@@ -250,3 +250,75 @@ def test_beyond_2m_tokens_partials_longer_than_16384(d):
         err = normwise(as64(x[:, :, idx]), r)
         print("N%d d%d" % (N, d), name, err, flush=True)
         assert err < TOL["bf16"]
+
+
+def test_long_context_2m_tokens_fp32_fwd_bwd():
+    # The fp32 half of the 2M-token target: B1 H8 N2,097,152 d128 fp32,
+    # inputs N(0, var 0.5), upstream gradient N(0,1), in the launch
+    # configuration the benchmark times (512 partials of 4,096 tokens per
+    # head).  One head against the oracle at the fp32 tolerance: S and z
+    # over all N tokens; O, dQ, dK, dV on 2,048 sampled rows including the
+    # first and the last, their references taken from the exact dS and dz
+    # over all N tokens (2,048 rows of dV = phi(K) dS and dK = (V dS^T +
+    # dz) phi'(K) pin the GPU's dS and dz).
+    dev = require_gpu()
+    B, H, N, d = 1, 8, 2097152, 128
+    print("B1 H8 N2097152 d128 fp32 fwd+bwd", flush=True)
+    xs = [torch.empty((B, H, N, d), dtype=torch.float32, device=dev) for _ in range(4)]
+    for sid, x in enumerate(xs):
+        la.gen_fill(x, seed=1002, stream_id=sid, std=(0.5 ** 0.5 if sid < 3 else 1.0))
+    o, S, z = la.forward(*xs[:3], return_summary=True)
+    dq, dk, dv = la.backward(*xs[:3], S, z, xs[3])
+    torch.cuda.synchronize()
+    h = 3
+    hq, hk, hv, hg = (to_host(x[:, h:h + 1]) for x in xs)
+    S_ref, z_ref = oracle.summary(hk, hv)
+    eS = normwise(S[:, h:h + 1].cpu().numpy(), S_ref)
+    ez = normwise(z[:, h:h + 1].cpu().numpy()[..., None], z_ref[..., None])
+    print("fp32 2M S", eS, "z", ez, flush=True)
+    assert eS < TOL["fp32"] and ez < TOL["fp32"]
+    _, dS_ref, dz_ref = oracle.backward_query(hq, hg, S_ref, z_ref, want_dq=False)
+    rows = np.sort(np.random.default_rng(3).choice(N, 2048, replace=False))
+    rows[0], rows[-1] = 0, N - 1
+    sel = lambda a: np.ascontiguousarray(a[:, :, rows])
+    o_ref = oracle.apply(sel(hq), S_ref, z_ref)
+    rdq, _, _ = oracle.backward_query(sel(hq), sel(hg), S_ref, z_ref)
+    rdk, rdv = oracle.backward_key(sel(hk), sel(hv), dS_ref, dz_ref)
+    idx = torch.from_numpy(rows).to(dev)
+    for name, x, r in (("o", o, o_ref), ("dq", dq, rdq), ("dk", dk, rdk), ("dv", dv, rdv)):
+        err = normwise(as64(x[:, h:h + 1, idx]), r)
+        print("fp32 2M", name, err, max_rel(as64(x[:, h:h + 1, idx]), r), flush=True)
+        assert err < TOL["fp32"]
+    # column sums of dV equal those of G at any size, every head
+    lhs = dv.double().sum(2)
+    rhs = xs[3].double().sum(2)
+    assert ((lhs - rhs).norm(dim=-1) / rhs.norm(dim=-1)).max().item() < TOL["fp32"]
+
+
+def test_autograd_sum_loss_and_transposed_upstream_gradient():
+    # loss = O.sum() hands the backward an expanded gradient of ones (all
+    # strides 0); a gradient held as [B, N, H, d] storage arrives as a
+    # permuted view.  Both reach the kernels in q's layout.
+    dev = require_gpu()
+    shape = (2, 3, 1500, 64)
+    q, k, v = make_inputs(shape, "bf16", 42)
+    tq, tk, tv = (to_device(x, dev).requires_grad_(True) for x in (q, k, v))
+    la.linear_attention(tq, tk, tv).sum().backward()
+    torch.cuda.synchronize()
+    ones = np.full(shape, 0x3F80, np.uint16)  # bf16 1.0
+    refs = oracle.backward(q, k, v, ones)
+    for name, x, r in zip(("dq", "dk", "dv"), (tq.grad, tk.grad, tv.grad), refs):
+        err = normwise(as64(x), r)
+        print("sum loss", name, err, flush=True)
+        assert err < TOL["bf16"], (name, err)
+    (g,) = make_inputs((2, 1500, 3, 64), "bf16", 43, streams=(3,))
+    tg = to_device(g, dev).permute(0, 2, 1, 3)
+    for t in (tq, tk, tv):
+        t.grad = None
+    la.linear_attention(tq, tk, tv).backward(tg)
+    torch.cuda.synchronize()
+    refs = oracle.backward(q, k, v, np.ascontiguousarray(g.transpose(0, 2, 1, 3)))
+    for name, x, r in zip(("dq", "dk", "dv"), (tq.grad, tk.grad, tv.grad), refs):
+        err = normwise(as64(x), r)
+        print("transposed gradient", name, err, flush=True)
+        assert err < TOL["bf16"], (name, err)

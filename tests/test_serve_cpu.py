@@ -205,3 +205,101 @@ def test_poisson_driver_reports_latency_percentiles():
     assert res["completed"] == 30 and res["failed"] == 0
     assert res["p50_ms"] <= res["p99_ms"] <= res["max_ms"]
     assert res["p50_ms"] >= 1.0  # at least the slice time
+
+
+def test_late_failure_keeps_the_slice_memory_until_its_work_drains():
+    # a slice that fails after its inputs were enqueued: the work already on
+    # its stream may still write the slice's block, so the block (and the
+    # request's FAILED state) wait until that work has drained
+    H, N, d = 1, 4096, 64
+    with serve.Server(1 << 30, max_slots=2, max_members_per_slice=1, fake_slice_ns=150 * MS) as srv:
+        srv.pause()
+        rid = srv.submit(serve.desc_for(2, H, N, d), gen_seed=1)
+        srv.fail_slice(rid, 0, late=True)
+        srv.pause(False)
+        time.sleep(0.03)
+        c = srv.stats()
+        kept = H * N * d * 2 * 2 + 2 * H * d * d * 8  # generated O of 2 members + S
+        assert c.in_flight_slices == 2            # the failed slice is still held
+        assert c.bytes_in_use > kept + 3 * H * N * d * 2
+        assert srv.poll(rid).state == serve.RUNNING
+        r = srv.wait(rid)
+        assert r.state == serve.FAILED and r.error == 4
+        assert r.t_done_ns - r.t_admit_ns >= 150 * MS
+        c = srv.stats()
+        assert c.in_flight_slices == 0 and c.failed == 1
+        srv.release(rid)
+        assert srv.stats().bytes_in_use == 0
+
+
+def test_early_failure_releases_at_once():
+    with serve.Server(1 << 30, max_slots=1, fake_slice_ns=200 * MS) as srv:
+        srv.pause()
+        rid = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1)
+        srv.fail_slice(rid, 0)
+        srv.pause(False)
+        r = srv.wait(rid, timeout_s=5)
+        assert r.state == serve.FAILED and r.t_done_ns - r.t_admit_ns < 150 * MS
+
+
+def test_summary_reuse_waits_for_its_owner_and_pins_it():
+    # one member's diffusion steps: the forward once, then apply-only steps
+    # against its summary; the owner cannot be released while steps are
+    # pending, and steps start only after the owner is DONE
+    with serve.Server(1 << 30, max_slots=4, fake_slice_ns=20 * MS,
+                      max_slices_per_request=1) as srv:
+        owner = srv.submit(serve.desc_for(2, 2, 4096, 64), gen_seed=10)
+        steps = [srv.submit(serve.desc_for(2, 2, 1000 + i, 64), gen_seed=11 + i,
+                            reuse_summary_of=owner) for i in range(3)]
+        with pytest.raises(B.LaError) as e:
+            srv.release(owner)
+        assert e.value.status == 7
+        ro = srv.wait(owner)
+        assert ro.state == serve.DONE                   # (fake executor: no device pointers)
+        res = [srv.wait(s) for s in steps]
+        for r in res:
+            assert r.state == serve.DONE
+            assert r.t_admit_ns >= ro.t_done_ns         # after the summary exists
+        for s in steps:
+            srv.release(s)
+        srv.release(owner)                              # now allowed
+        assert srv.stats().bytes_in_use == 0
+
+
+def test_summary_reuse_errors_and_failed_owner():
+    with serve.Server(1 << 30, max_slots=1, fake_slice_ns=5 * MS) as srv:
+        with pytest.raises(B.LaError) as e:
+            srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1, reuse_summary_of=999)
+        assert e.value.status == 5                      # unknown owner
+        srv.pause()
+        owner = srv.submit(serve.desc_for(2, 1, 1024, 64), gen_seed=1)
+        for bad in (serve.desc_for(3, 1, 1024, 64), serve.desc_for(2, 2, 1024, 64),
+                    serve.desc_for(2, 1, 1024, 32), serve.desc_for(2, 1, 1024, 64, dtype=1)):
+            with pytest.raises(B.LaError) as e:
+                srv.submit(bad, gen_seed=2, reuse_summary_of=owner)
+            assert e.value.status == 1                  # B, H, d, dtype must match
+        step = srv.submit(serve.desc_for(2, 1, 5000, 64), gen_seed=2, reuse_summary_of=owner)
+        with pytest.raises(B.LaError):                  # no chains of reuse
+            srv.submit(serve.desc_for(2, 1, 64, 64), gen_seed=3, reuse_summary_of=step)
+        srv.fail_slice(owner, 0)
+        srv.pause(False)
+        assert srv.wait(owner).state == serve.FAILED
+        r = srv.wait(step)
+        assert r.state == serve.FAILED and r.error == 4  # the owner's error
+        srv.release(step)
+        srv.release(owner)
+        with pytest.raises(B.LaError):                  # a FAILED owner is refused
+            owner2 = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=4)
+            srv.fail_slice(owner2, 0)
+            srv.wait(owner2)
+            srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=5, reuse_summary_of=owner2)
+
+
+def test_destroy_cancels_pending_reusers():
+    srv = serve.Server(1 << 30, max_slots=1, fake_slice_ns=30 * MS)
+    owner = srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=1)
+    for i in range(3):
+        srv.submit(serve.desc_for(1, 1, 1024, 64), gen_seed=2 + i, reuse_summary_of=owner)
+    t0 = time.monotonic()
+    srv.close()
+    assert time.monotonic() - t0 < 1.0
