@@ -128,6 +128,27 @@ la_status la_forward(const la_attn_desc* desc, const void* q, const void* k,
                      void* ws, size_t ws_bytes, la_stream stream);
 
 /*
+ * The forward pass for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): la_forward with its workspace taken from a fixed array of
+ * LA_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device
+ * until the process ends, so the call itself allocates nothing.  Arguments
+ * and results are those of la_forward (same kernels, so the same bits);
+ * the array of the CURRENT device is used, and `stream` must belong to that
+ * device.  LA_ERR_OOM when la_workspace_size(desc, 0) exceeds the array
+ * (bf16 inputs: 8 heads at d = 128 fit up to 4,079,616 tokens each,
+ * 64 heads at d = 64 up to 1,982,464; fp32 inputs, 8 heads at d = 128: up
+ * to 1,019,904).  All calls on one device share its
+ * array: calls whose work overlaps on the device (different streams, or
+ * other host threads, without ordering between them) race on it and must
+ * be serialised by the caller.
+ */
+#define LA_NOALLOC_SCRATCH_BYTES (128u << 20)
+la_status la_forward_noalloc(const la_attn_desc* desc, const void* q, const void* k,
+                             const void* v, void* o, double* s_out, double* z_out,
+                             la_stream stream);
+
+/*
  * Apply a given summary: O_i = phi(q_i)^T S / (phi(q_i) . z) for every query,
  * with S [B][H][d][d] and z [B][H][d] FP64 (dense) from an earlier
  * la_forward (s_out, z_out).  This is the per-step work when the keys and

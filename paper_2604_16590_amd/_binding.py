@@ -180,6 +180,28 @@ def forward(q, k, v, out_dtype=None, return_summary=False, out=None):
     return (out, S, z) if return_summary else out
 
 
+def forward_noalloc(q, k, v, out, S, z):
+    """la_forward_noalloc: the forward pass into caller-allocated out, S
+    [B,H,d,d] and z [B,H,d] (float64), with the library's fixed device
+    scratch as workspace, so the call allocates nothing."""
+    _same_layout(q, k, "k")
+    _same_layout(q, v, "v")
+    B, H, N, d = q.shape
+    if S.shape != (B, H, d, d) or z.shape != (B, H, d) or S.dtype != torch.float64 \
+            or z.dtype != torch.float64 or not (S.is_contiguous() and z.is_contiguous()):
+        raise ValueError("S must be [B,H,d,d] and z [B,H,d], contiguous float64")
+    desc = make_desc(q, out)
+    L = lib()
+    if not getattr(L, "_noalloc_typed", False):
+        L.la_forward_noalloc.argtypes = [ctypes.POINTER(AttnDesc), VP, VP, VP, VP, VP, VP, VP]
+        L.la_forward_noalloc.restype = ctypes.c_int
+        L._noalloc_typed = True
+    _check("la_forward_noalloc", L.la_forward_noalloc(
+        ctypes.byref(desc), q.data_ptr(), k.data_ptr(), v.data_ptr(), out.data_ptr(),
+        S.data_ptr(), z.data_ptr(), _stream(q.device)))
+    return out
+
+
 def apply(q, S, z, out_dtype=None, out=None):
     """O from queries and a summary (S, z) computed earlier by forward()."""
     if not q.is_cuda:

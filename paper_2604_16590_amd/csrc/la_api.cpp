@@ -217,6 +217,14 @@ la_status apply_impl(const la_attn_desc* desc, const void* q, const double* s, c
 
 }  // namespace
 
+namespace la {
+// A failed HIP call seen outside this file: kept for la_last_hip_error().
+int32_t record_hip_error(int32_t e) {
+  g_last_hip_error = e;
+  return LA_ERR_HIP;
+}
+}  // namespace la
+
 extern "C" {
 
 const char* la_status_string(la_status s) {

@@ -218,6 +218,9 @@ struct BwdArgs {
 enum { MODE_FWD = 0, MODE_BWD = 1 };
 enum { PART_SUMMARY = 0, PART_BLOCKS = 1 };  // layouts of per-wave partial sums
 
+// Keeps a failed hipError_t for la_last_hip_error(); returns LA_ERR_HIP.
+int32_t record_hip_error(int32_t e);
+
 hipError_t launch_forward(const FwdArgs& a);
 // Apply only: images of a given S (into a.img), then the apply kernel.
 hipError_t launch_apply(const FwdArgs& a);

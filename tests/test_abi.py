@@ -199,3 +199,17 @@ def test_stream_probe_rejects_bad_arguments_before_gpu_work():
     assert L.la_stream_probe(1, None, b + 4, 64, 0, None) == 1  # misaligned destination
     assert L.la_stream_probe(2, a, a + 16, 64, 0, None) == 1    # overlapping copy
     assert L.la_stream_probe(3, a, b, 64, 0, None) == 1         # unknown kind
+
+
+def test_noalloc_forward_checks_before_touching_the_device():
+    # descriptor errors, and problems whose workspace exceeds the fixed
+    # scratch (LA_ERR_OOM), are reported before any HIP call
+    L = la.lib()
+    L.la_forward_noalloc.argtypes = [ctypes.POINTER(B.AttnDesc)] + [ctypes.c_void_p] * 7
+    L.la_forward_noalloc.restype = ctypes.c_int
+    fake = 1 << 20
+    assert L.la_forward_noalloc(ctypes.byref(desc(N=0)), fake, fake, fake, fake, None, None, None) == 1
+    N, H = 4 << 20, 64
+    big = B.AttnDesc(1, H, N, 64, 0, 0, H * N * 64, N * 64, 64, H * N * 64, N * 64, 64, 0, 0)
+    assert ws_status(big)[1] > (128 << 20)
+    assert L.la_forward_noalloc(ctypes.byref(big), fake, fake, fake, fake, None, None, None) == 3
