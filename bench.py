@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-others", action="store_true", help="skip the other workload shapes")
+    ap.add_argument("--serve-window", type=int, default=200,
+                    help="arrivals per serving point (the 2,000-arrival window takes minutes)")
     ap.add_argument("--cpu-tokens", type=int, default=262144,
                     help="tokens per head of the oracle sample (8 heads, d = 128)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -186,11 +188,12 @@ def other_workloads(steps):
     import torch
     import paper_2604_16590_amd as la
     out = {}
-    for name, (B, H, N, d), bwd in (("fwd_bwd_B2_H16_N262144_d64", (2, 16, 262144, 64), True),
-                                    ("fwd_B4_H16_N16384_d64", (4, 16, 16384, 64), False)):
+    for name, (B, H, N, d), bwd, grid in (
+            ("fwd_bwd_B2_H16_N262144_d64", (2, 16, 262144, 64), True, None),
+            ("fwd_B4_H16_N16384_d64", (4, 16, 16384, 64), False, (8, 32, 64))):
         xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device="cuda:0") for _ in range(4)]
         for sid, x in enumerate(xs):
-            la.gen_fill(x, seed=1001, stream_id=sid)
+            la.gen_fill(x, seed=1001, stream_id=sid, grid=grid if sid < 3 else None)
         plan = la.Plan(*xs[:3], dout=xs[3])
 
         def step():
@@ -200,6 +203,13 @@ def other_workloads(steps):
 
         t = time_steps(step, max(steps, 20), 3)
         out[name] = {"tokens_per_s": round(B * N / t, 1), "ms_per_step": round(t * 1e3, 4)}
+        if not bwd:
+            # the small grid (537 MB moved) fits largely in the 256 MB
+            # Infinity Cache across back-to-back steps: time it also with L2
+            # and the Infinity Cache flushed before every step (a 1 GiB write
+            # stream), each step bracketed by its own events, median of >= 20
+            out[name].update(flushed_step(plan.forward, max(steps, 20), B * N,
+                                          4 * B * H * N * d * 2))
         log("%s %.3f ms" % (name, t * 1e3))
         del plan, xs
         torch.cuda.empty_cache()
@@ -246,7 +256,74 @@ def other_workloads(steps):
     log("tiles: extract %.3f ms, blend %.3f ms" % (t_ex * 1e3, t_bl * 1e3))
     del field, tiles
     torch.cuda.empty_cache()
+
+    # the whole tiled step on the same grid, 16 heads of d = 64: fused
+    # (la_tiled_forward: tile summaries read K, V in place, one pass reads Q
+    # and writes O) against the composition that materialises the tiles
+    H, d = 16, 64
+    qkv = []
+    for sid in range(3):
+        x = torch.empty(dims + (H, d), dtype=torch.bfloat16, device="cuda:0")
+        la.gen_fill(x.view(1, 1, -1, H * d), seed=1004, stream_id=sid)
+        qkv.append(x)
+    o = torch.empty_like(qkv[0])
+    fused = lambda: la.tiled_forward(*qkv, core, halo, out=o)
+    t_f = time_steps(fused, max(steps, 10), 2)
+    la.profile_enable(True)
+    for _ in range(5):
+        fused()
+    kst = la.profile_read()
+    la.profile_enable(False)
+    t_u = time_steps(lambda: la.tiled_attention(*qkv, core, halo), 3, 1)
+    nbytes = 4 * fb
+    out["tiled_step_T256_Y64_X128_H16_d64"] = {
+        "core": core, "halo": halo, "fused_ms": round(t_f * 1e3, 4),
+        "fused_tokens_per_s": round(dims[0] * dims[1] * dims[2] / t_f, 1),
+        "alg_GB": round(nbytes / 1e9, 3), "fused_GB_s": round(nbytes / t_f / 1e9, 1),
+        "fused_frac_of_hbm_peak": round(nbytes / t_f / 1e9 / HBM_PEAK_GBS, 4),
+        "fused_kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kst.items()},
+        "unfused_ms": round(t_u * 1e3, 4)}
+    log("tiled step: fused %.3f ms, unfused %.3f ms" % (t_f * 1e3, t_u * 1e3))
+    del qkv, o
+    torch.cuda.empty_cache()
     return out
+
+
+def flushed_step(fn, steps, tokens, nbytes):
+    """Median time of fn() with the caches flushed before each call, and a
+    per-kernel breakdown from a second pass under the kernel timer.  The
+    flush reads 1 GiB (four times the Infinity Cache): a flush by writing
+    would leave the caches full of dirty lines whose write-back then lands
+    in the timed call."""
+    import torch
+    import paper_2604_16590_amd as la
+    flush = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+    sink = torch.empty(64, dtype=torch.uint8, device="cuda:0")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for i in range(3):
+        la.stream_probe("read", sink, flush)
+        fn()
+    for i, (e0, e1) in enumerate(ev):
+        la.stream_probe("read", sink, flush)
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    med = ms[len(ms) // 2]
+    la.profile_enable(True)
+    for i in range(steps):
+        la.stream_probe("read", sink, flush)
+        fn()
+    stats = la.profile_read()
+    la.profile_enable(False)
+    del flush
+    kern = {k: round(v[1] / v[0], 4) for k, v in stats.items() if not k.startswith("stream_")}
+    return {"flushed_ms_median": round(med, 4), "flushed_tokens_per_s": round(tokens / (med * 1e-3), 1),
+            "flushed_GB_s": round(nbytes / (med * 1e-3) / 1e9, 1),
+            "flushed_frac_of_hbm_peak": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "flushed_kernels_ms": kern}
 
 
 def cpu_model():
@@ -260,45 +337,86 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(n_tokens):
-    """The FP64 oracle (as it stands) on a bounded sample of the workload:
-    B1 H8 n_tokens d128 bf16, forward + backward; also the GPU's normwise
-    error on that same sample."""
+def oracle_sample(shape, dtype, seed, std, backward=True, grid=None):
+    """The FP64 oracle (as it stands) on one seeded sample: seconds of host
+    time, and the GPU path's normwise errors on the same inputs (max over
+    (b, h) of ||X - X_ref|| / ||X_ref||)."""
     import numpy as np
     import torch
     import oracle
     import paper_2604_16590_amd as la
-    w = WORKLOAD
-    shape = (1, w["H"], n_tokens, w["d"])
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
     xs = []
-    for sid in range(4):
-        x = torch.empty(shape, dtype=torch.bfloat16, device="cuda:0")
-        la.gen_fill(x, seed=77, stream_id=sid, std=w["std_qkv"] if sid < 3 else 1.0)
+    for sid in range(4 if backward else 3):
+        x = torch.empty(shape, dtype=tdt, device="cuda:0")
+        la.gen_fill(x, seed=seed, stream_id=sid, std=std if sid < 3 else 1.0, grid=grid)
         xs.append(x)
     torch.cuda.synchronize()
-    host = [x.cpu().view(torch.int16).numpy().view(np.uint16) for x in xs]
+
+    def host(x):
+        x = x.cpu()
+        return x.view(torch.int16).numpy().view(np.uint16) if dtype == "bf16" else x.numpy()
+
+    hx = [host(x) for x in xs]
     oracle._load()
     t0 = time.perf_counter()
-    o_ref = oracle.forward(*host[:3])
-    dq_r, dk_r, dv_r = oracle.backward(*host)
+    o_ref = oracle.forward(*hx[:3])
+    refs = oracle.backward(*hx) if backward else None
     dt = time.perf_counter() - t0
-    plan = la.Plan(*xs[:3], dout=xs[3])
+    plan = la.Plan(*xs[:3], dout=xs[3] if backward else None)
     plan.forward()
-    plan.backward()
+    if backward:
+        plan.backward()
     torch.cuda.synchronize()
+    lead = shape[0] * shape[1]
 
     def err(t, ref):
-        a = t.float().cpu().numpy().astype(np.float64)
-        num = np.linalg.norm((a - ref).reshape(shape[1], -1), axis=1)
-        return float((num / np.linalg.norm(ref.reshape(shape[1], -1), axis=1)).max())
+        a = t.float().cpu().numpy().astype(np.float64).reshape(lead, -1)
+        r = ref.reshape(lead, -1)
+        return float((np.linalg.norm(a - r, axis=1) / np.linalg.norm(r, axis=1)).max())
 
-    errors = {"o": err(plan.o, o_ref), "dq": err(plan.dq, dq_r), "dk": err(plan.dk, dk_r),
-              "dv": err(plan.dv, dv_r)}
+    errors = {"o": err(plan.o, o_ref)}
+    if backward:
+        for name, t, r in zip(("dq", "dk", "dv"), (plan.dq, plan.dk, plan.dv), refs):
+            errors[name] = err(t, r)
+    del plan, xs
+    torch.cuda.empty_cache()
+    return dt, errors
+
+
+def cpu_baseline(n_tokens):
+    """The FP64 oracle on a bounded sample of the bench workload (B1 H8
+    n_tokens d128 bf16, forward + backward), with the GPU's errors on it."""
+    import oracle
+    w = WORKLOAD
+    shape = (1, w["H"], n_tokens, w["d"])
+    dt, errors = oracle_sample(shape, "bf16", 77, w["std_qkv"])
     return {
         "value": round(n_tokens / dt, 1), "unit": "tokens/s", "cores": oracle.threads(),
         "kind": "oracle", "cpu": cpu_model(),
         "sample": "fwd+bwd, B1 H8 N%d d128 bf16 N(0,0.5) inputs, FP64 oracle, %.1f s" % (n_tokens, dt),
     }, errors
+
+
+def cpu_baseline_other_workloads():
+    """The oracle on the other workload shapes (whole configurations where
+    they take seconds, else a stated sample), tokens/s counting a token
+    through all H heads, with the GPU's errors on the same inputs."""
+    out = {}
+    cases = (
+        # name, shape run, heads of the configuration, dtype, backward, grid
+        ("fwd_B1_H1_N4096_d64_fp32", (1, 1, 4096, 64), 1, "fp32", False, None),
+        ("fwd_B4_H16_N16384_d64", (4, 16, 16384, 64), 16, "bf16", False, (8, 32, 64)),
+        ("fwd_bwd_B2_H16_N262144_d64", (1, 2, 262144, 64), 16, "bf16", True, None),
+    )
+    for name, shape, H_all, dtype, bwd, grid in cases:
+        dt, errors = oracle_sample(shape, dtype, 1001, 1.0, backward=bwd, grid=grid)
+        tokens = shape[0] * shape[2] * shape[1] / H_all  # tokens through all heads
+        out[name] = {"tokens_per_s": round(tokens / dt, 1), "oracle_s": round(dt, 3),
+                     "sample": "B%d H%d N%d d%d %s%s" % (shape + (dtype, ", fwd+bwd" if bwd else "")),
+                     "errors_vs_oracle": errors}
+        log("oracle %s: %.2f s" % (name, dt))
+    return out
 
 
 def main():
@@ -408,6 +526,12 @@ def main():
         log("fp32 fwd+bwd %.3f ms" % (t32 * 1e3))
         del p32, xs
         torch.cuda.empty_cache()
+        if not args.no_cpu_baseline:
+            # the fp32 path against the oracle on a sample of the workload
+            # (2 of the 8 heads, 65,536 tokens, the same distributions)
+            _, fp32["errors_vs_oracle_on_sample"] = oracle_sample(
+                (1, 2, 65536, w["d"]), "fp32", 78, w["std_qkv"])
+            fp32["errors_sample"] = "fwd+bwd, B1 H2 N65536 d128 fp32 N(0,0.5) inputs"
 
     # ---- serving (ensemble-member requests, continuous batching) ----
     serve = None
@@ -415,7 +539,7 @@ def main():
         from paper_2604_16590_amd import serve as serve_mod
         log("serving: Poisson stream of ensemble requests")
         try:
-            serve = serve_mod.bench_summary()
+            serve = serve_mod.bench_summary(n_requests=args.serve_window)
         except Exception as ex:  # reported, not hidden: the line says what failed
             serve = {"error": "%s: %s" % (type(ex).__name__, ex)}
         torch.cuda.empty_cache()
@@ -423,9 +547,12 @@ def main():
     # ---- oracle on the host cores, plus the GPU's error on that sample ----
     cpu = None
     errors = None
+    cpu_others = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         cpu, errors = cpu_baseline(args.cpu_tokens)
+        if not args.no_others:
+            cpu_others = cpu_baseline_other_workloads()
 
     result = {
         "metric": METRIC,
@@ -457,6 +584,7 @@ def main():
         "serve": serve,
         "cpu_baseline": cpu,
         "errors_vs_oracle_on_sample": errors,
+        "cpu_baseline_other_workloads": cpu_others,
     }
     print(json.dumps(result), flush=True)
 

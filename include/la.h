@@ -249,6 +249,31 @@ la_status la_tile_extract(const la_tile_desc* desc, const void* field, void* til
 la_status la_tile_blend(const la_tile_desc* desc, const void* tiles, void* field,
                         la_stream stream);
 
+/*
+ * The whole tiled attention step in two passes over the fields, with no
+ * tile materialised: q, k, v, o are [T][Y][X][C] fields (C = heads * d
+ * channels, head h in channels [h*d, h*d + d)), bf16, 16-byte aligned,
+ * device, caller-owned.  The result is that of extracting the q, k, v
+ * tiles, running la_forward with the tiles as the batch and blending the
+ * tile outputs with la_tile_blend:
+ *     o(p) = sum_t w_t(p) O_t(p) / sum_t w_t(p),
+ *     O_t(p) = phi(q_p)^T S_t / (phi(q_p) . z_t),
+ * S_t, z_t the summary over tile t's extended, border-clamped token set,
+ * w_t the tile's Hann weight at p -- except that the tile outputs O_t are
+ * kept in FP32 instead of being rounded to bf16, and S_t enters as its bf16
+ * hi part (about 2^-9 relative; z_t as hi + lo).  Pass 1 reads K and V in
+ * place and keeps per (tile, head) only S_t, z_t as matrix-core operands;
+ * pass 2 reads Q once and writes O once.  Requirements beyond
+ * la_tile_desc's: dtype LA_BF16, d = C / heads in {16, 32, 64},
+ * 2 * halo <= core in every dimension (then each position lies in at most
+ * two tiles per dimension) and at most 65,536 tokens per extended tile;
+ * otherwise LA_ERR_UNSUPPORTED.
+ * ws: ws_bytes >= la_tiled_workspace_size(desc, heads), 256-byte aligned.
+ */
+la_status la_tiled_workspace_size(const la_tile_desc* desc, int64_t heads, size_t* bytes);
+la_status la_tiled_forward(const la_tile_desc* desc, int64_t heads, const void* q, const void* k,
+                           const void* v, void* o, void* ws, size_t ws_bytes, la_stream stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request loop for ensemble members.
  *

@@ -492,6 +492,35 @@ def tiled_attention(q, k, v, core, halo):
     return tile_blend(to, (T, Y, X), core, halo).view(T, Y, X, H, d)
 
 
+def tiled_forward(q, k, v, core, halo, out=None):
+    """The tiled attention step of tiled_attention() in two fused passes
+    (la_tiled_forward): q, k, v [T, Y, X, H, d] bf16 tensors, contiguous;
+    no tile is materialised."""
+    for t in (q, k, v):
+        if t.dim() != 5 or not t.is_contiguous() or t.shape != q.shape or t.dtype != q.dtype:
+            raise ValueError("q, k, v must be contiguous [T, Y, X, H, d] tensors of one shape")
+    T, Y, X, H, d = q.shape
+    desc = _tile_desc((T, Y, X), core, halo, H * d, q.dtype)
+    L = lib()
+    if not getattr(L, "_tiled_typed", False):
+        P = ctypes.POINTER
+        L.la_tiled_workspace_size.argtypes = [P(TileDesc), ctypes.c_int64, P(ctypes.c_size_t)]
+        L.la_tiled_forward.argtypes = [P(TileDesc), ctypes.c_int64, VP, VP, VP, VP, VP,
+                                       ctypes.c_size_t, VP]
+        L.la_tiled_workspace_size.restype = ctypes.c_int
+        L.la_tiled_forward.restype = ctypes.c_int
+        L._tiled_typed = True
+    n = ctypes.c_size_t(0)
+    _check("la_tiled_workspace_size", L.la_tiled_workspace_size(ctypes.byref(desc), H, ctypes.byref(n)))
+    ws = _workspace(n.value, q.device)
+    if out is None:
+        out = torch.empty_like(q)
+    _check("la_tiled_forward", L.la_tiled_forward(
+        ctypes.byref(desc), H, q.data_ptr(), k.data_ptr(), v.data_ptr(), out.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream(q.device)))
+    return out
+
+
 STREAM_KINDS = {"read": 0, "write": 1, "copy": 2}
 
 

@@ -26,7 +26,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 LIBS = {
     "liblagen.so": ["gen.hip"],
     "liblinattn.so": ["la_api.cpp", "la_forward.hip", "la_backward.hip", "la_serve.cpp",
-                      "la_profile.cpp", "la_tiles.hip", "la_probe.hip", "la_noalloc.hip"],
+                      "la_profile.cpp", "la_tiles.hip", "la_probe.hip", "la_noalloc.hip", "la_tiled.hip"],
 }
 
 

@@ -58,7 +58,6 @@ la_status check_desc(const la_attn_desc* d) {
 struct Tiling {
   int P;   // partial sums per (b, h)
   int Tw;  // tokens per partial (a multiple of 64, at most max_fp32_run)
-  int Ta;  // tokens per apply workgroup
   int Tk;  // tokens per workgroup of the key (and two-pass query) backward
 };
 
@@ -69,7 +68,10 @@ struct Tiling {
 int64_t max_fp32_run(int dt) { return dt == LA_BF16 ? 16384 : 4096; }
 
 Tiling choose_tiling(int64_t N, int d, int dt) {
-  const int64_t tw_min = d >= 128 ? 2048 : 1024;
+  // at least 2048 (d = 128) or 512 tokens per partial: the 16,384-token
+  // grid shape (64 heads, d = 64) gave 0.151 / 0.146 / 0.159 ms for its
+  // cache-flushed forward at 1024 / 512 / 256
+  const int64_t tw_min = d >= 128 ? 2048 : 512;
   // at most 128 partials at d = 128 and 64 below while that keeps each
   // FP32 run within max_fp32_run: longer ranges per wave paid off at d = 64
   // (summary of 32 heads x 262,144 tokens 0.38 -> 0.33 ms), while 8 heads
@@ -88,11 +90,18 @@ Tiling choose_tiling(int64_t N, int d, int dt) {
   t.P = (int)P;
   t.Tw = (int)Tw;
   // per-token kernels: no cross-token sums, so these ranges change no bits
-  // (measured: apply is fastest at 4096 tokens per workgroup, the key
-  // backward at 2048)
-  t.Ta = (int)std::min<int64_t>(4096, ceil_div(N, 64) * 64);
+  // (measured: the key backward is fastest at 2048 tokens per workgroup)
   t.Tk = (int)std::min<int64_t>(2048, ceil_div(N, 64) * 64);
   return t;
+}
+
+// Apply workgroups per head: about kApplyGrid in the whole grid (a few per
+// compute unit), at most one per token block.  Per-token work, so this
+// changes no bits and may depend on the batch size.
+int apply_groups(int64_t N, int64_t BH, int dt, int d) {
+  const int64_t blk = dt == LA_FP32 && d >= 128 ? 64 : 128;  // tokens per block
+  int64_t grid = 4096;
+  return (int)std::max<int64_t>(1, std::min(ceil_div(N, blk), ceil_div(grid, BH)));
 }
 
 // Bytes of the two matrix-core operand images of one head.
@@ -147,6 +156,14 @@ Layout layout_for(const la_attn_desc* d, int pass) {
 }
 
 // The gate's arguments (the attention's own are checked by the caller).
+// Key-backward workgroups per head, as apply_groups (the fp32 path at
+// d = 128 takes one tile per wave step, like the apply).
+int key_groups(int64_t N, int64_t BH, int dt, int d) {
+  const int64_t blk = dt == LA_FP32 ? 64 : 128;  // tokens per block (4 waves x 16 x TT)
+  int64_t grid = 8192;
+  return (int)std::max<int64_t>(1, std::min(ceil_div(N, blk), ceil_div(grid, BH)));
+}
+
 la_status check_gate(const void* other, const double* sigma, double sigma_data) {
   if (!other || !sigma) return LA_ERR_INVALID_ARG;
   if (!aligned16(other) || ((uintptr_t)sigma & 7u)) return LA_ERR_INVALID_ARG;
@@ -174,7 +191,8 @@ la_status forward_impl(const la_attn_desc* desc, const void* q, const void* k, c
   a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
   a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
   a.q = q; a.k = k; a.v = v; a.o = o;
-  a.P = t.P; a.Tw = t.Tw; a.Ta = t.Ta;
+  a.P = t.P; a.Tw = t.Tw;
+  a.Ga = apply_groups(desc->N, desc->B * desc->H, desc->in_dtype, (int)desc->d);
   a.part = (float*)(w + L.part);
   a.S64 = s_out ? s_out : (double*)(w + L.S64);
   a.z64 = z_out ? z_out : (double*)(w + L.z64);
@@ -204,7 +222,7 @@ la_status apply_impl(const la_attn_desc* desc, const void* q, const double* s, c
   a.sb = desc->in_sb; a.sh = desc->in_sh; a.sn = desc->in_sn;
   a.osb = desc->out_sb; a.osh = desc->out_sh; a.osn = desc->out_sn;
   a.q = q; a.o = o;
-  a.Ta = t.Ta;
+  a.Ga = apply_groups(desc->N, desc->B * desc->H, desc->in_dtype, (int)desc->d);
   a.S64 = const_cast<double*>(s);
   a.z64 = const_cast<double*>(z);
   a.img = (char*)ws + L.img;
@@ -312,6 +330,7 @@ la_status la_backward(const la_attn_desc* desc, const void* q, const void* k,
   a.dq = dq; a.dk = dk; a.dv = dv;
   a.S64 = s; a.z64 = z;
   a.P = t.P; a.Tw = t.Tw; a.Ta = t.Tk;
+  a.Gk = key_groups(desc->N, desc->B * desc->H, desc->in_dtype, (int)desc->d);
   a.img = w + L.img;
   a.part = (float*)(w + L.part);
   a.stash = (float2*)(w + L.stash);

@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // ---------------------------------------------------------------------------
 // Fused query backward (bf16 inputs, d = 32 or 64): dQ exactly as in the
 // query kernel, and in the same pass each wave's partial sums over its own
-// token range [p*Tw, p*Tw + Tw) of
+// tokens (32-token blocks p, p + P, ..., at most Tw tokens) of
 //   dS = sum_i phi(q_i) (G_i / den_i)^T,   dz = sum_i dden_i phi(q_i),
 // so Q and G are read once.  The reduction contracts over tokens, but the
 // query pass holds one token per lane; the token-major operands are made
@@ -406,8 +406,11 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
   const int g = lane >> 4, n = lane & 15;
   const int p = blockIdx.x * 4 + wave;
   if (p >= P) return;  // no barriers follow
-  const int64_t t_begin = (int64_t)p * Tw;
-  const int64_t t_end = min(N, t_begin + (int64_t)Tw);
+  // partial p takes the head's 32-token blocks p, p + P, p + 2P, ... (at
+  // most Tw tokens), so the grid's waves move through Q, G and dQ together
+  const int64_t nb = (N + 16 * TT - 1) / (16 * TT);
+  const int nsteps = (int)((nb - 1 - p) / P + 1);  // >= 1: P <= N / 64 < nb
+  auto first_token = [&](int k) { return ((int64_t)p + (int64_t)k * P) * (16 * TT); };
 
   const int64_t row_bytes = sn * 2, orow_bytes = osn * OES;
   const char* qh = (const char*)q + (b * sb + h * sh) * 2;
@@ -418,12 +421,12 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
   u32x4* stg = stage + wave * (FC::STAGE / 16);
 
   // Prefetch a step's Q and G runs into this wave's LDS stage: slot
-  // [(tt*2 + tensor)*NCH + chunk][lane].  Rows past the range are skipped
-  // (their slots keep stale data; the reader zeroes those tokens).
+  // [(tt*2 + tensor)*NCH + chunk][lane].  Rows past the head's end are
+  // skipped (their slots keep stale data; the reader zeroes those tokens).
   auto prefetch = [&](int64_t t0) {
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      const bool ok = t0 + 16 * tt + n < t_end;
+      const bool ok = t0 + 16 * tt + n < N;
 #pragma unroll
       for (int ten = 0; ten < 2; ++ten) {
         const char* src = (ten == 0 ? qh : gh) + (t0 + 16 * tt) * row_bytes + ioff;
@@ -459,10 +462,11 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 #pragma unroll
   for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
 
-  prefetch(t_begin);
+  prefetch(first_token(0));
   // the first step's inputs (no stores are in flight yet)
   wait_vmem<0>();
-  for (int64_t t0 = t_begin; t0 < t_end; t0 += 16 * TT) {
+  for (int kstep = 0; kstep < nsteps; ++kstep) {
+    const int64_t t0 = first_token(kstep);
     // this step's runs: wait for its prefetch, issued before the previous
     // step's NSTORE dQ stores (the counter retires in issue order, so at
     // most NSTORE outstanding means the prefetch has landed), read them,
@@ -471,7 +475,7 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
     uint32_t pq[TT][RW], pg[TT][RW];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      const bool ok = t0 + 16 * tt + n < t_end;
+      const bool ok = t0 + 16 * tt + n < N;
       uint32_t qw[RW];
 #pragma unroll
       for (int w = 0; w < NCH; ++w) {
@@ -485,7 +489,7 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
       phi_words<DT_BF16, D>(qw, pq[tt]);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    if (t0 + 16 * TT < t_end) prefetch(t0 + 16 * TT);
+    if (kstep + 1 < nsteps) prefetch(first_token(kstep + 1));
 
     // X = S G and den = phi(q) . z on the matrix cores
     f32x4 acc[TT][NT];
@@ -532,7 +536,7 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
       rdt[tt] = rd;
       ddt[tt] = -go * rd;        // zero for padded tokens (G = 0)
       const int64_t t = t0 + 16 * tt + n;
-      const bool ok = t < t_end;
+      const bool ok = t < N;
       // dQ chunk by chunk (few live registers): run positions [CH*w, +CH)
       constexpr int CH = RN::CH;
       constexpr int OCB = CH * OES;
@@ -607,8 +611,8 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
 
 // ---------------------------------------------------------------------------
 // Fused query backward at d = 128 (bf16): the four waves of a workgroup
-// share one partial (token range [p*Tw, p*Tw + Tw)), taking 16-token tiles
-// in turn (64 tokens per step); two workgroups fit a compute unit, so one
+// share one partial (64-token blocks p, p + P, ..., at most Tw tokens),
+// taking 16-token tiles in turn (one block per step); two workgroups fit a compute unit, so one
 // waiting at a barrier leaves the SIMDs to the other.  Each wave does the
 // query pass for its tile and makes its tile's token-major operands (as in
 // bwd_qds_kernel, by selection products) into LDS; after a barrier, wave w
@@ -655,10 +659,13 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
+  // partial p (this workgroup) takes the head's 64-token blocks p, p + P,
+  // p + 2P, ... (at most Tw tokens), so the grid moves through Q, G and dQ
+  // together; the step count is the same for all waves
   const int p = blockIdx.x;
-  const int64_t t_begin = (int64_t)p * Tw;
-  const int64_t t_end = min(N, t_begin + (int64_t)Tw);
-  const int nsteps = (int)((t_end - t_begin + 16 * NW - 1) / (16 * NW));  // the same for all waves
+  const int64_t nb = (N + 16 * NW - 1) / (16 * NW);
+  const int nsteps = (int)((nb - 1 - p) / P + 1);  // >= 1: P <= N / 64 <= nb
+  auto block_token = [&](int k) { return ((int64_t)p + (int64_t)k * P) * (16 * NW); };
 
   const int64_t row_bytes = sn * 2, orow_bytes = osn * OES;
   const char* qh = (const char*)q + (b * sb + h * sh) * 2;
@@ -667,12 +674,12 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   const uint32_t ooff = (uint32_t)n * (uint32_t)orow_bytes + (uint32_t)(g * OCB);
 
   typedef uint32_t Regs[2][RW];  // Q run, G run of this wave's tile
-  // Rows past the partial's end read its last token again (finite values,
-  // no zero fill); the step gives such tokens a zero scale, so they add
+  // Rows past the head's end read its last token again (finite values, no
+  // zero fill); the step gives such tokens a zero scale, so they add
   // nothing to dS or dz and their dQ rows are not stored.
   auto load = [&](int k, Regs& x) {
-    const int64_t tb = min(t_begin + 16 * NW * k + 16 * wave, t_end - 1);  // wave-uniform
-    const int last = (int)min((int64_t)15, t_end - 1 - tb);
+    const int64_t tb = min(block_token(k) + 16 * wave, N - 1);  // wave-uniform
+    const int last = (int)min((int64_t)15, N - 1 - tb);
     const uint32_t off = (uint32_t)min(n, last) * (uint32_t)row_bytes + (uint32_t)(g * RN::CB);
     load_run<D, DT_BF16>(qh + tb * row_bytes + off, x[0]);
     load_run<D, DT_BF16>(gh + tb * row_bytes + off, x[1]);
@@ -702,7 +709,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   }
 
   auto step = [&](int k, const Regs& x) {
-    const int64_t tb = t_begin + 16 * NW * k + 16 * wave;
+    const int64_t tb = block_token(k) + 16 * wave;
     uint32_t pq[RW];
     phi_words<DT_BF16, D>(x[0], pq);
     const uint32_t* pg = x[1];
@@ -735,7 +742,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
                                  sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
       ((u32x2*)&xb[wave >> 1][j][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
-    const bool ok = tb + n < t_end;
+    const bool ok = tb + n < N;
     const double rden = 1.0 / (double)dacc[0];
     const float rd = ok ? (float)rden : 0.f;  // zero past the end: no dS, dz share
     // G . O = phi(q) . X / den per token
@@ -856,13 +863,16 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
 // ---------------------------------------------------------------------------
 // Key kernel: dV = phi(K) dS (T image of dS) and dK = (V dS^T + dz) phi'(K)
 // (N image of dS).  WHICH: 1 = dV only, 2 = dK only, 3 = both.
-// The dS operands are the hi parts of the bf16 images.
+// The dS operands are the hi parts of the bf16 images.  As in the apply,
+// the G workgroups of a head take its blocks of 4 * 16 * TT tokens in turn
+// (blocks g, g + G, ...), so the whole grid moves through the tensors
+// together.
 // ---------------------------------------------------------------------------
 template <int DT, int OT, int D, int WHICH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_key_kernel(
     const void* __restrict__ k, const void* __restrict__ v, int64_t sb, int64_t sh,
     int64_t sn, void* __restrict__ dk, void* __restrict__ dv, int64_t osb, int64_t osh,
-    int64_t osn, int H, int64_t N, int Ta, const void* __restrict__ dimg,
+    int64_t osn, int H, int64_t N, int G, const void* __restrict__ dimg,
     const double* __restrict__ dz64) {
   using C = RowCfg<DT, D>;
   using IC = ImageCfg<D>;
@@ -889,8 +899,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   }
   __syncthreads();
 
-  const int64_t wg_begin = (int64_t)blockIdx.x * Ta;
-  const int64_t wg_end = min(N, wg_begin + (int64_t)Ta);
   const int64_t in_head = (b * sb + h * sh) * C::ES + (int64_t)g * Run<D, DT>::CB;
   const char* kbase = (const char*)k + in_head;
   const char* vbase = (const char*)v + in_head;
@@ -898,7 +906,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 
   auto load_one = [&](int64_t t0, uint32_t* kw, uint32_t* vw) {
     const int64_t t = t0 + n;
-    if (t < wg_end) {
+    if (t < N) {
       load_run<D, DT>(kbase + t * sn * C::ES, kw);
       if (DO_K) load_run<D, DT>(vbase + t * sn * C::ES, vw);
     } else {
@@ -911,18 +919,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
     for (int tt = 0; tt < (C::PF ? TT : 1); ++tt) load_one(t0 + 16 * tt, kw[tt], vw[tt]);
   };
+  constexpr int BLK = 16 * TT * 4;  // tokens per block
+  const int64_t nblk = (N + BLK - 1) / BLK;
+  const int64_t blk0 = blockIdx.x;
+  const int nk = blk0 < nblk ? (int)((nblk - 1 - blk0) / G + 1) : 0;
+  // first token of this wave's part of the k-th block it takes
+  auto tok = [&](int kk) { return (blk0 + (int64_t)kk * G) * BLK + 16 * TT * wave; };
   uint32_t kcur[C::PF ? TT : 1][C::RWD], vcur[C::PF ? TT : 1][C::RWD];
-  const int64_t first = wg_begin + 16 * TT * wave;
   if constexpr (C::PF) {
-    if (first < wg_end) load(first, kcur, vcur);
+    if (nk > 0) load(tok(0), kcur, vcur);
   }
-  for (int64_t t0 = first; t0 < wg_end; t0 += 16 * TT * 4) {
+  for (int kk = 0; kk < nk; ++kk) {
+    const int64_t t0 = tok(kk);
     // next step's inputs are in flight while this step computes
     uint32_t knext[C::PF ? TT : 1][C::RWD], vnext[C::PF ? TT : 1][C::RWD];
-    const bool more = C::PF && t0 + 16 * TT * 4 < wg_end;
+    const bool more = C::PF && kk + 1 < nk;
     uint32_t pk[TT][C::PW], pv[TT][C::PW];
     if constexpr (C::PF) {
-      if (more) load(t0 + 16 * TT * 4, knext, vnext);
+      if (more) load(tok(kk + 1), knext, vnext);
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
         phi_words<DT, D>(kcur[tt], pk[tt]);
@@ -948,7 +962,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
         const int64_t t = t0 + 16 * tt + n;
-        if (t < wg_end) {
+        if (t < N) {
           float out[Q4];
 #pragma unroll
           for (int i = 0; i < NT; ++i)
@@ -968,7 +982,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
       for (int tt = 0; tt < TT; ++tt) {
         const int64_t t = t0 + 16 * tt + n;
-        if (t < wg_end) {
+        if (t < N) {
           float out[Q4];
 #pragma unroll
           for (int i = 0; i < NT; ++i)
@@ -1027,16 +1041,17 @@ static void launch_rows(const BwdArgs& a) {
   }
   // both dS images fit in LDS except fp32 at d = 128 (2 x 64 KB): two passes
   ProfScope prof("bwd_key", a.stream);
+  const dim3 kgrid((unsigned)a.Gk, BH);
   if constexpr (DT == DT_FP32 && D >= 128) {
-    bwd_key_kernel<DT, OT, D, 1><<<grid, 256, 0, a.stream>>>(
-        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+    bwd_key_kernel<DT, OT, D, 1><<<kgrid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Gk,
         a.dimg, a.dz64);
-    bwd_key_kernel<DT, OT, D, 2><<<grid, 256, 0, a.stream>>>(
-        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+    bwd_key_kernel<DT, OT, D, 2><<<kgrid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Gk,
         a.dimg, a.dz64);
   } else {
-    bwd_key_kernel<DT, OT, D, 3><<<grid, 256, 0, a.stream>>>(
-        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta,
+    bwd_key_kernel<DT, OT, D, 3><<<kgrid, 256, 0, a.stream>>>(
+        a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Gk,
         a.dimg, a.dz64);
   }
 }

@@ -185,7 +185,8 @@ struct FwdArgs {
   int64_t sb, sh, sn, osb, osh, osn;
   const void *q, *k, *v;
   void* o;
-  int P, Tw, Ta;       // partials per head, tokens per partial, tokens per apply workgroup
+  int P, Tw;           // partials per head, tokens per partial
+  int Ga;              // apply workgroups per head (they take its token blocks in turn)
   float* part;         // [BH][P][D*D + D]
   double* S64;         // [BH][D][D]
   double* z64;         // [BH][D]
@@ -205,7 +206,8 @@ struct BwdArgs {
   const void *q, *k, *v, *dout;
   void *dq, *dk, *dv;
   const double *S64, *z64;
-  int P, Tw, Ta;
+  int P, Tw, Ta;       // Ta: tokens per workgroup of the two-pass query kernel
+  int Gk;              // key-backward workgroups per head (they take its token blocks in turn)
   void* img;           // images of S
   float* part;         // partials of dS, dz
   float2* stash;       // [BH][N] per query token: (1/den, -(dO . O))

@@ -5,10 +5,11 @@
 // one; the key backward reads two and writes two).  These three streams
 // measure what a plain kernel of each mix reaches on the device at hand, so
 // the attention kernels' rates can be read against a ceiling measured the
-// same way rather than only against the nominal peak.  As in the attention
-// kernels, each wave streams a contiguous chunk of its own (16-byte words,
-// four in flight per lane); the words past the last whole chunk are spread
-// over all lanes.
+// same way rather than only against the nominal peak.  Reads and writes
+// stream a contiguous chunk per wave (16-byte words, four in flight per
+// lane); the copy sweeps the buffer with the whole grid, the form of the
+// apply and key-backward kernels; in both the words past the last whole
+// chunk or block are spread over all lanes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -89,24 +90,29 @@ __global__ __launch_bounds__(kThreads) void stream_write_kernel(u32x4* __restric
   for (int64_t i = tail_begin(s); i < s.n; i += stride) dst[i] = v;
 }
 
-template <bool NT>
-__global__ __launch_bounds__(kThreads) void stream_copy_kernel(const u32x4* __restrict__ src,
-                                                               u32x4* __restrict__ dst, Split s) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// Copy with the grid sweeping the buffer together: consecutive waves take
+// consecutive blocks of 64 * U words (one 16-byte word per lane per load),
+// so the accesses in flight at any moment lie in a narrow window of the
+// buffer; the words past the last whole block are spread over all lanes.
+template <int U, bool NT>
+__global__ __launch_bounds__(kThreads) void stream_copy_swept_kernel(const u32x4* __restrict__ src,
+                                                                     u32x4* __restrict__ dst,
+                                                                     int64_t n) {
+  constexpr int64_t BLK = 64 * U;
   const int lane = threadIdx.x & 63;
-  if (w < s.waves) {
-    const u32x4* p = src + w * s.per_wave + lane;
-    u32x4* q = dst + w * s.per_wave + lane;
-    for (int64_t i = 0; i < s.per_wave; i += kStep) {
-      u32x4 v[kUnroll];
+  const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+  const int64_t full = n / BLK * BLK;
+  for (int64_t base = wave * BLK; base < full; base += waves * BLK) {
+    u32x4 v[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) v[u] = load_word<NT>(p + i + 64 * u);
+    for (int u = 0; u < U; ++u) v[u] = load_word<NT>(src + base + 64 * u + lane);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) store_word<NT>(v[u], q + i + 64 * u);
-    }
+    for (int u = 0; u < U; ++u) store_word<NT>(v[u], dst + base + 64 * u + lane);
   }
   const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t i = tail_begin(s); i < s.n; i += stride) dst[i] = src[i];
+  for (int64_t i = full + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
 }
 
 // `waves` chunks of whole kStep groups; fewer waves when the buffer is small
@@ -135,11 +141,13 @@ extern "C" la_status la_stream_probe(int32_t kind, const void* src, void* dst, s
   }
   if (kind != LA_STREAM_READ && kind != LA_STREAM_WRITE && kind != LA_STREAM_COPY)
     return LA_ERR_INVALID_ARG;
-  // Per kind, the fastest form measured on a 4 GiB buffer (wave counts 1024
-  // to 8192, with and without nontemporal accesses): reads with nontemporal
-  // loads at two waves per SIMD (7.07 TB/s), writes with plain stores at
-  // two waves per SIMD (5.94 TB/s), copies nontemporal at eight waves per
-  // SIMD (5.22 TB/s).
+  // Per kind, the fastest form measured on a 4 GiB buffer (one contiguous
+  // chunk per wave at 2048 to 16384 waves, with and without nontemporal
+  // accesses, bursts of 8 and 16 words per lane, and grid-swept forms):
+  // reads with nontemporal loads at two waves per SIMD (7.02 TB/s), writes
+  // with plain stores at two waves per SIMD (5.97 TB/s), copies grid-swept,
+  // eight nontemporal words per lane, 8192 workgroups (5.49 TB/s; one
+  // chunk per wave reached 5.21, bursts 5.31).
   const hipStream_t st = (hipStream_t)stream;
   const int64_t n = (int64_t)(bytes / 16);
   auto grid = [](const Split& s) { return dim3((unsigned)std::max<int64_t>(1, (s.waves + 3) / 4)); };
@@ -155,10 +163,10 @@ extern "C" la_status la_stream_probe(int32_t kind, const void* src, void* dst, s
     hipLaunchKernelGGL(stream_write_kernel<false>, grid(s), dim3(kThreads), 0, st, (u32x4*)dst, s,
                        pattern);
   } else {
-    const Split s = split_words(n, 8192);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(8192, n / (8 * 256)));
     la::ProfScope prof("stream_copy", st);
-    hipLaunchKernelGGL(stream_copy_kernel<true>, grid(s), dim3(kThreads), 0, st, (const u32x4*)src,
-                       (u32x4*)dst, s);
+    hipLaunchKernelGGL((stream_copy_swept_kernel<8, true>), dim3((unsigned)blocks), dim3(kThreads),
+                       0, st, (const u32x4*)src, (u32x4*)dst, n);
   }
   return hipGetLastError() == hipSuccess ? LA_OK : LA_ERR_HIP;
 }

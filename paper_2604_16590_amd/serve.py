@@ -210,6 +210,49 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
                                       "attention": attn_ms / max(1, len(ok))}}
 
 
+def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, caller_q=None):
+    """One request's diffusion loop against a fixed history (temporal
+    cross-attention, Sec. III-B; 80 steps per ensemble sample, Sec. V):
+    the summary of its server-generated keys and values once, then `steps`
+    apply-only requests reusing it, each submitted when the previous one is
+    DONE (a step needs the previous step's output).  Queries are generated
+    by the server (stream 0 of a per-step seed) or, with caller_q = a list
+    of (q, o) device pointer pairs used in turn, caller-owned (attention
+    only).  Step latency runs from submission to DONE."""
+    desc = desc_for(members, H, N, d)
+    owner = server.submit(desc, gen_seed=seed)
+    r0 = server.wait(owner)
+    if r0.state != DONE:
+        server.release(owner)
+        return {"error": "summary request failed (%d)" % r0.error}
+    lat, gen, attn, failed = [], [], [], 0
+    for i in range(steps):
+        t0 = time.monotonic_ns()
+        if caller_q:
+            q, o = caller_q[i % len(caller_q)]
+            rid = server.submit(desc, q=q, o=o, t_arrival_ns=t0, reuse_summary_of=owner)
+        else:
+            rid = server.submit(desc, gen_seed=seed + 1 + i, t_arrival_ns=t0,
+                                reuse_summary_of=owner)
+        r = server.wait(rid)
+        if r.state == DONE:
+            lat.append((r.t_done_ns - t0) / 1e6)
+            gen.append(r.gen_ms)
+            attn.append(r.attn_ms)
+        else:
+            failed += 1
+        server.release(rid)
+    server.release(owner)
+    return {"steps": steps, "completed": len(lat), "failed": failed,
+            "summary_ms": (r0.t_done_ns - r0.t_arrival_ns) / 1e6,
+            "step_p50_ms": percentile(lat, 50), "step_p99_ms": percentile(lat, 99),
+            "step_max_ms": max(lat) if lat else None,
+            "loop_ms": sum(lat),
+            "device_ms_per_step": {"generation": sum(gen) / max(1, len(gen)),
+                                   "attention": sum(attn) / max(1, len(attn))},
+            "tokens_per_s": members * N * len(lat) / (sum(lat) * 1e-3) if lat else None}
+
+
 def bench_summary(budget_gb=200, n_requests=200):
     """Serving measurement for the benchmark: the literal 200 req/s Poisson
     stream (saturating; a bounded window of `n_requests` arrivals) and a
@@ -221,8 +264,15 @@ def bench_summary(budget_gb=200, n_requests=200):
         sub = run_poisson(srv, n_requests, 0.7 * cap, seed=6)
         c = srv.stats()
         peak = c.peak_bytes_in_use
+        # diffusion loops reusing one summary: one member, and a whole
+        # 64-member ensemble request (N = 262,144 tokens, H16 d64)
+        loop1 = run_reuse_loop(srv, members=1)
+        loop64 = run_reuse_loop(srv, members=64)
     return {"workload": "Poisson arrivals, N log-uniform [4096, 1048576], 64 members, "
                         "H16 d64 bf16, server-generated N(0,1) inputs, budget %d GB" % budget_gb,
             "saturated_200rps": sat, "sub_saturation": sub,
             "p50_ms": sub["p50_ms"], "p99_ms": sub["p99_ms"],
-            "peak_budget_bytes": peak}
+            "peak_budget_bytes": peak,
+            "reuse_loop_80_steps": {"workload": "1 summary + 80 apply-only steps, N262144 H16 d64 "
+                                                "bf16, server-generated queries per step",
+                                    "members_1": loop1, "members_64": loop64}}

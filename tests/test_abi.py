@@ -213,3 +213,27 @@ def test_noalloc_forward_checks_before_touching_the_device():
     big = B.AttnDesc(1, H, N, 64, 0, 0, H * N * 64, N * 64, 64, H * N * 64, N * 64, 64, 0, 0)
     assert ws_status(big)[1] > (128 << 20)
     assert L.la_forward_noalloc(ctypes.byref(big), fake, fake, fake, fake, None, None, None) == 3
+
+
+def test_tiled_forward_argument_checks():
+    # the fused tiled step supports bf16, d <= 64 and halos of at most half
+    # a core; everything else is refused before any device work
+    L = la.lib()
+    T3 = ctypes.c_int64 * 3
+    L.la_tiled_workspace_size.argtypes = [ctypes.POINTER(B.TileDesc), ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+    L.la_tiled_workspace_size.restype = ctypes.c_int
+
+    def ws(dims, core, halo, C, dtype, heads):
+        d = B.TileDesc(T3(*dims), T3(*core), T3(*halo), C, dtype)
+        n = ctypes.c_size_t(0)
+        return L.la_tiled_workspace_size(ctypes.byref(d), heads, ctypes.byref(n)), n.value
+
+    st, n = ws((16, 32, 64), (4, 16, 16), (2, 8, 8), 256, 0, 4)
+    assert st == 0 and n > 0
+    assert ws((16, 32, 64), (4, 16, 16), (2, 8, 8), 256, 1, 4)[0] == 2    # fp32
+    assert ws((16, 32, 64), (4, 16, 16), (2, 8, 8), 256, 0, 2)[0] == 2    # d = 128
+    assert ws((16, 32, 64), (4, 16, 16), (3, 8, 8), 256, 0, 4)[0] == 2    # halo > core / 2
+    assert ws((16, 32, 64), (4, 16, 16), (2, 8, 8), 256, 0, 3)[0] == 1    # C % heads
+    assert ws((16, 32, 64), (4, 16, 16), (5, 8, 8), 256, 0, 4)[0] == 1    # halo > core
+    assert ws((64, 64, 64), (64, 32, 40), (0, 0, 0), 256, 0, 4)[0] == 2   # > 65,536 tokens a tile

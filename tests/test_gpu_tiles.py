@@ -77,3 +77,60 @@ def test_one_tile_is_global_attention():
     a = out.reshape(T * Y * X, H, d)
     b = glob[0].permute(1, 0, 2)
     assert torch.allclose(a, b, rtol=1e-6, atol=1e-7)
+
+
+def oracle_tiled(q, k, v, dims, core, halo, H, d):
+    """The tiled step composed in the oracle (FP64): extract, attention per
+    tile (tiles as the batch, heads in the channels), Hann blend."""
+    n, L = la.tile_geometry(dims, core, halo)
+    N = L[0] * L[1] * L[2]
+    tiles = [oracle.tile_extract(as64(a), core, halo).reshape(n, N, H, d).transpose(0, 2, 1, 3)
+             for a in (q, k, v)]
+    o_tiles = oracle.forward(*(np.ascontiguousarray(t) for t in tiles))
+    o_tiles = o_tiles.transpose(0, 2, 1, 3).reshape((n,) + L + (H * d,))
+    return oracle.tile_blend(o_tiles, dims, core, halo)
+
+
+FUSED = [((2, 16, 24), (1, 8, 8), (0, 2, 3), 2, 32),     # ragged x tiles
+         ((4, 9, 13), (2, 4, 5), (1, 2, 2), 3, 16),      # ragged everywhere
+         ((3, 16, 32), (2, 8, 16), (1, 4, 8), 2, 64),    # halos of half a core
+         ((8, 8, 16), (8, 8, 16), (0, 0, 0), 1, 64),     # one tile: global attention
+         ((5, 7, 11), (3, 3, 4), (0, 1, 2), 4, 16)]
+
+
+@pytest.mark.parametrize("dims,core,halo,H,d", FUSED)
+def test_fused_tiled_forward_matches_oracle_composition(dims, core, halo, H, d):
+    # the whole step in two passes (no tile stored) against the oracle's
+    # extract -> attention per tile -> blend
+    dev = require_gpu()
+    T, Y, X = dims
+    q, k, v = (field(dims, H * d, "bf16", s) for s in (51, 52, 53))
+    tq, tk, tv = (to_device(a, dev).view(T, Y, X, H, d) for a in (q, k, v))
+    print("fused tiled", dims, core, halo, H, d, flush=True)
+    out = la.tiled_forward(tq, tk, tv, core, halo)
+    unfused = la.tiled_attention(tq, tk, tv, core, halo)
+    torch.cuda.synchronize()
+    ref = oracle_tiled(q, k, v, dims, core, halo, H, d)
+    err = normwise(as64(out).reshape(1, 1, -1), ref.reshape(1, 1, -1))
+    err_unfused = normwise(as64(unfused).reshape(1, 1, -1), ref.reshape(1, 1, -1))
+    print("  normwise: fused", err, "unfused", err_unfused, flush=True)
+    assert err < TOL["bf16"]
+    # the same arithmetic up to the bf16 rounding of the unfused tile outputs
+    # (and S_t as its hi part here): both within a few 1e-3 of each other
+    assert normwise(as64(out).reshape(1, 1, -1), as64(unfused).reshape(1, 1, -1)) < 1e-2
+
+
+def test_fused_tiled_forward_bitwise_deterministic_and_full_grid_shape():
+    # the paper's per-frame 32 x 64 patch grid, 16 frames, 4 heads of d = 64
+    dev = require_gpu()
+    dims, core, halo, H, d = (16, 32, 64), (4, 16, 16), (2, 8, 8), 4, 64
+    q, k, v = (field(dims, H * d, "bf16", s) for s in (54, 55, 56))
+    tq, tk, tv = (to_device(a, dev).view(*dims, H, d) for a in (q, k, v))
+    a = la.tiled_forward(tq, tk, tv, core, halo)
+    b = la.tiled_forward(tq, tk, tv, core, halo)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ref = oracle_tiled(q, k, v, dims, core, halo, H, d)
+    err = normwise(as64(a).reshape(1, 1, -1), ref.reshape(1, 1, -1))
+    print("fused tiled 16x32x64 normwise", err, flush=True)
+    assert err < TOL["bf16"]

@@ -303,3 +303,11 @@ def test_destroy_cancels_pending_reusers():
     t0 = time.monotonic()
     srv.close()
     assert time.monotonic() - t0 < 1.0
+
+
+def test_reuse_loop_driver_reports_step_percentiles():
+    with serve.Server(1 << 30, max_slots=2, fake_slice_ns=MS) as srv:
+        res = serve.run_reuse_loop(srv, steps=12, members=2, H=2, N=4096, d=32)
+        assert res["completed"] == 12 and res["failed"] == 0
+        assert MS / 1e6 <= res["step_p50_ms"] <= res["step_p99_ms"] <= res["step_max_ms"]
+        assert srv.stats().bytes_in_use == 0
