@@ -154,16 +154,69 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+class InputPool:
+    """Caller-owned, pre-generated N(0, 1) bf16 inputs for attention-only
+    serving: Q, K, V and O each one [H, T, d] tensor (T = `tokens`, 64 x
+    262,144 by default: 34 GB per tensor at H16 d64).  A request of B
+    members and N tokens reads and writes windows of it: member b, head h
+    covers tokens [base + b*s, base + b*s + N) of head h, with s = N while
+    B*N fits in T (disjoint windows) and s = (T - N) / (B - 1) beyond that
+    (neighbouring members' windows overlap; the time between two members
+    reaching the same token is far longer than the caches hold it).  The
+    base is drawn per request, so consecutive small requests do not land
+    on the same cached bytes.  Outputs of requests in flight at the same
+    time share the O pool: the pool serves throughput, not results (the
+    served results are checked with server-generated inputs)."""
+
+    def __init__(self, H=16, d=64, tokens=64 * 262144, seed=11):
+        import torch
+        self.H, self.d, self.T = H, d, int(tokens)
+        self.t = {}
+        for sid, name in enumerate(("q", "k", "v", "o")):
+            x = torch.empty((H, self.T, d), dtype=torch.bfloat16, device="cuda")
+            if name != "o":
+                B.gen_fill(x.view(1, H, self.T, d), seed=seed, stream_id=sid)
+            self.t[name] = x
+        torch.cuda.synchronize()
+
+    def request(self, members, N, rng):
+        """(desc, q, k, v, o pointers) of one request's windows."""
+        H, d, T = self.H, self.d, self.T
+        if N > T:
+            raise ValueError("request of %d tokens exceeds the pool (%d)" % (N, T))
+        s = N if members * N <= T else (T - N) // max(1, members - 1)
+        span = (members - 1) * s + N
+        base = int(rng.integers(0, T - span + 1))
+        desc = B.AttnDesc(members, H, N, d, B.LA_BF16, B.LA_BF16, s * d, T * d, d,
+                          s * d, T * d, d, B.LA_PHI_ELU1, 0)
+        off = base * d * 2
+        return (desc,) + tuple(self.t[n].data_ptr() + off for n in ("q", "k", "v", "o"))
+
+    def free(self):
+        import torch
+        self.t = {}
+        torch.cuda.empty_cache()
+
+
+def request_bytes(members, H, N, d, esize=2):
+    """HBM bytes a forward request moves: K and V read by the summary, Q
+    read and O written by the apply."""
+    return 4 * members * H * N * d * esize
+
+
 def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
-                n_min=4096, n_max=1048576, dtype=B.LA_BF16):
+                n_min=4096, n_max=1048576, dtype=B.LA_BF16, pool=None):
     """Open-loop arrivals: exponential inter-arrival times at `rate_per_s`,
     token counts log-uniform in [n_min, n_max], each request `members`
-    ensemble members with server-generated N(0, 1) inputs.  Latency runs from
-    the scheduled arrival time to completion (no coordinated omission)."""
+    ensemble members with server-generated N(0, 1) inputs, or, with `pool`
+    (an InputPool), caller-owned inputs read from it (attention only).
+    Latency runs from the scheduled arrival time to completion (no
+    coordinated omission)."""
     import numpy as np
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_per_s, n_requests)
     ns = np.round(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_requests))).astype(np.int64)
+    place = np.random.default_rng(seed + 1)
     t0 = time.monotonic_ns() + 2_000_000
     arrivals = t0 + (np.cumsum(gaps) * 1e9).astype(np.int64)
     ids, pending = [], {}
@@ -172,8 +225,13 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
     while i < n_requests or pending:
         now = time.monotonic_ns()
         while i < n_requests and arrivals[i] <= now:
-            desc = desc_for(members, H, int(ns[i]), d, dtype)
-            rid = server.submit(desc, gen_seed=1000 + i, gen_std=1.0, t_arrival_ns=int(arrivals[i]))
+            if pool is None:
+                desc = desc_for(members, H, int(ns[i]), d, dtype)
+                rid = server.submit(desc, gen_seed=1000 + i, gen_std=1.0,
+                                    t_arrival_ns=int(arrivals[i]))
+            else:
+                desc, q, k, v, o = pool.request(members, int(ns[i]), place)
+                rid = server.submit(desc, q, k, v, o, t_arrival_ns=int(arrivals[i]))
             pending[rid] = int(ns[i])
             ids.append(rid)
             i += 1
@@ -205,22 +263,36 @@ def run_poisson(server, n_requests, rate_per_s, seed, H=16, d=64, members=64,
             "max_ms": max(lat) if lat else None,
             "tokens_per_s": tokens / span if span > 0 else None,
             "req_per_s": len(lat) / span if span > 0 else None,
+            # the attention's own HBM bytes (K, V, Q read; O written) per
+            # second of the window
+            "attention_TB_s": (request_bytes(1, H, 1, d) * tokens / span / 1e12
+                               if span > 0 else None),
             "window_s": span,
             "device_ms_per_request": {"generation": gen_ms / max(1, len(ok)),
                                       "attention": attn_ms / max(1, len(ok))}}
 
 
-def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, caller_q=None):
+def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, caller_q=None,
+                   pool=None):
     """One request's diffusion loop against a fixed history (temporal
     cross-attention, Sec. III-B; 80 steps per ensemble sample, Sec. V):
-    the summary of its server-generated keys and values once, then `steps`
-    apply-only requests reusing it, each submitted when the previous one is
-    DONE (a step needs the previous step's output).  Queries are generated
-    by the server (stream 0 of a per-step seed) or, with caller_q = a list
-    of (q, o) device pointer pairs used in turn, caller-owned (attention
-    only).  Step latency runs from submission to DONE."""
+    the summary of its keys and values once, then `steps` apply-only
+    requests reusing it, each submitted when the previous one is DONE (a
+    step needs the previous step's output).  Inputs are generated by the
+    server (queries: stream 0 of a per-step seed), or caller-owned: with
+    caller_q = a list of (q, o) device pointer pairs used in turn, or with
+    `pool` (an InputPool) the summary's K, V and every step's Q, O taken
+    from windows of the pool (attention only).  Step latency runs from
+    submission to DONE."""
     desc = desc_for(members, H, N, d)
-    owner = server.submit(desc, gen_seed=seed)
+    place = None
+    if pool is not None:
+        import numpy as np
+        place = np.random.default_rng(seed)
+        desc, q0, k0, v0, o0 = pool.request(members, N, place)
+        owner = server.submit(desc, q0, k0, v0, o0)
+    else:
+        owner = server.submit(desc, gen_seed=seed)
     r0 = server.wait(owner)
     if r0.state != DONE:
         server.release(owner)
@@ -228,7 +300,10 @@ def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, ca
     lat, gen, attn, failed = [], [], [], 0
     for i in range(steps):
         t0 = time.monotonic_ns()
-        if caller_q:
+        if pool is not None:
+            sdesc, q, _, _, o = pool.request(members, N, place)
+            rid = server.submit(sdesc, q=q, o=o, t_arrival_ns=t0, reuse_summary_of=owner)
+        elif caller_q:
             q, o = caller_q[i % len(caller_q)]
             rid = server.submit(desc, q=q, o=o, t_arrival_ns=t0, reuse_summary_of=owner)
         else:
@@ -253,11 +328,15 @@ def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, ca
             "tokens_per_s": members * N * len(lat) / (sum(lat) * 1e-3) if lat else None}
 
 
-def bench_summary(budget_gb=200, n_requests=200):
+def bench_summary(budget_gb=200, n_requests=200, attention_only=True):
     """Serving measurement for the benchmark: the literal 200 req/s Poisson
     stream (saturating; a bounded window of `n_requests` arrivals) and a
-    point at 0.7x the measured saturated throughput.  With 200 requests per
-    point the p99 sits above two samples rather than being the maximum."""
+    point at 0.7x the measured saturated throughput, with server-generated
+    inputs (the generator stands in for the upstream projection); then the
+    same two points with caller-owned inputs from an InputPool, where the
+    device time is attention only.  With 200 requests per point the p99
+    sits above two samples rather than being the maximum."""
+    import torch
     with Server(int(budget_gb * 1e9), max_slots=4, n_streams=4, max_slices_per_request=2) as srv:
         sat = run_poisson(srv, n_requests, 200.0, seed=5)
         cap = sat["req_per_s"] or 1.0
@@ -268,11 +347,29 @@ def bench_summary(budget_gb=200, n_requests=200):
         # 64-member ensemble request (N = 262,144 tokens, H16 d64)
         loop1 = run_reuse_loop(srv, members=1)
         loop64 = run_reuse_loop(srv, members=64)
-    return {"workload": "Poisson arrivals, N log-uniform [4096, 1048576], 64 members, "
-                        "H16 d64 bf16, server-generated N(0,1) inputs, budget %d GB" % budget_gb,
-            "saturated_200rps": sat, "sub_saturation": sub,
-            "p50_ms": sub["p50_ms"], "p99_ms": sub["p99_ms"],
-            "peak_budget_bytes": peak,
-            "reuse_loop_80_steps": {"workload": "1 summary + 80 apply-only steps, N262144 H16 d64 "
-                                                "bf16, server-generated queries per step",
-                                    "members_1": loop1, "members_64": loop64}}
+    out = {"workload": "Poisson arrivals, N log-uniform [4096, 1048576], 64 members, "
+                       "H16 d64 bf16, server-generated N(0,1) inputs, budget %d GB" % budget_gb,
+           "saturated_200rps": sat, "sub_saturation": sub,
+           "p50_ms": sub["p50_ms"], "p99_ms": sub["p99_ms"],
+           "peak_budget_bytes": peak,
+           "reuse_loop_80_steps": {"workload": "1 summary + 80 apply-only steps, N262144 H16 d64 "
+                                               "bf16, server-generated queries per step",
+                                   "members_1": loop1, "members_64": loop64}}
+    if attention_only:
+        torch.cuda.empty_cache()
+        pool = InputPool()
+        try:
+            # the arena holds only workspaces and the kept S, z here
+            with Server(16 << 30, max_slots=4, n_streams=4, max_slices_per_request=2) as srv:
+                a_sat = run_poisson(srv, n_requests, 200.0, seed=5, pool=pool)
+                a_cap = a_sat["req_per_s"] or 1.0
+                a_sub = run_poisson(srv, n_requests, 0.7 * a_cap, seed=6, pool=pool)
+                a_loop64 = run_reuse_loop(srv, members=64, pool=pool)
+        finally:
+            pool.free()
+        out["attention_only"] = {
+            "workload": "the same arrivals and request shapes; caller-owned pre-generated "
+                        "inputs read from one [16, 64 x 262144, 64] bf16 pool per tensor",
+            "saturated_200rps": a_sat, "sub_saturation": a_sub,
+            "reuse_loop_80_steps_members_64": a_loop64}
+    return out

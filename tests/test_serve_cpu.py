@@ -311,3 +311,63 @@ def test_reuse_loop_driver_reports_step_percentiles():
         assert res["completed"] == 12 and res["failed"] == 0
         assert MS / 1e6 <= res["step_p50_ms"] <= res["step_p99_ms"] <= res["step_max_ms"]
         assert srv.stats().bytes_in_use == 0
+
+
+class _Ptr:
+    def __init__(self, p):
+        self.p = p
+
+    def data_ptr(self):
+        return self.p
+
+
+def fake_pool(H, d, T):
+    pool = serve.InputPool.__new__(serve.InputPool)
+    pool.H, pool.d, pool.T = H, d, T
+    pool.t = {n: _Ptr((i + 1) << 40) for i, n in enumerate(("q", "k", "v", "o"))}
+    return pool
+
+
+@pytest.mark.parametrize("members,N", [(64, 4096), (64, 1000), (64, 262144), (64, 262145),
+                                       (64, 1048576), (1, 5000), (3, 16777206)])
+def test_input_pool_windows_stay_inside_the_pool(members, N):
+    # every member's window [base + b*s, base + b*s + N) lies in the pool;
+    # windows are disjoint while members * N fits, and the strides describe
+    # an [H, T, d] tensor
+    import numpy as np
+    H, d, T = 16, 64, 64 * 262144
+    pool = fake_pool(H, d, T)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        desc, q, k, v, o = pool.request(members, N, rng)
+        assert (desc.B, desc.H, desc.N, desc.d) == (members, H, N, d)
+        assert desc.in_sh == desc.out_sh == T * d and desc.in_sn == desc.out_sn == d
+        assert desc.in_sb == desc.out_sb and desc.in_sb % d == 0
+        s = desc.in_sb // d
+        base = (q - pool.t["q"].p) // (2 * d)
+        assert (q - pool.t["q"].p) % (2 * d) == 0
+        for name, p in zip(("k", "v", "o"), (k, v, o)):
+            assert p - pool.t[name].p == base * 2 * d
+        assert base >= 0 and base + (members - 1) * s + N <= T
+        if members * N <= T:
+            assert s == N
+        else:
+            assert 0 < s < N
+
+
+def test_input_pool_rejects_a_request_larger_than_the_pool():
+    import numpy as np
+    with pytest.raises(ValueError):
+        fake_pool(2, 64, 1000).request(1, 1001, np.random.default_rng(0))
+
+
+def test_poisson_and_reuse_drivers_with_caller_owned_pool():
+    pool = fake_pool(2, 32, 64 * 8192)
+    with serve.Server(8 << 30, max_slots=4, fake_slice_ns=MS) as srv:
+        res = serve.run_poisson(srv, 20, 500.0, seed=1, H=2, d=32, members=4,
+                                n_min=1024, n_max=8192, pool=pool)
+        assert res["completed"] == 20 and res["failed"] == 0
+        assert res["attention_TB_s"] > 0
+        loop = serve.run_reuse_loop(srv, steps=5, members=4, H=2, N=4096, d=32, pool=pool)
+        assert loop["completed"] == 5
+        assert srv.stats().bytes_in_use == 0
