@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = 4 * i + r;
-            const float dphi_c = fminf(run_val<DT>(pq[tt], c), 1.0f);
+            const float dphi_c = dphi_of_phi(run_val<DT>(pq[tt], c));
             out[c] = (float)(fma(-go, zr[c], (real)acc[tt][i][r]) * rd) * dphi_c;
           }
         store_run<D, DT, OT>(oh + (t0 + 16 * tt) * orow_bytes + ooff, out);
@@ -359,13 +359,25 @@ struct FusedCfg {
   static constexpr int NCH = R::NCH;                  // 16-byte chunks per run
   static constexpr int STAGE = TT * 2 * NCH * 1024;   // LDS bytes per wave per step
   static constexpr int WAVES_PER_SIMD = 2;
-  static constexpr int NSTORE = TT * NCH;             // dQ store instructions per step
 };
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4* lds_s16x4_ptr;
+
+// gfx950 transposing LDS read of 16-bit elements: within each 16-lane
+// block, lane i receives as element k (k = 0..3) element i & 3 of the
+// 8-byte chunk addressed by lane (i >> 2) + 4k of the block.  When lane L
+// of a block addresses token row t0 + (L >> 2), features f0 + 4 (L & 3)
+// .. + 3 of a row-major bf16 tile, lane i receives tokens t0 .. t0 + 3 of
+// feature f0 + i: a token-major matrix-core operand straight from LDS.
+__device__ __forceinline__ u32x2 lds_read_tr16(const void* p) {
+  const s16x4 r = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4_ptr)(p));
+  return __builtin_bit_cast(u32x2, r);
+}
 
 // Wait until at most N vector memory operations of this wave are
-// outstanding (they complete in issue order); also a compiler barrier.
+// outstanding; also a compiler barrier.
 template <int N>
 __device__ __forceinline__ void wait_vmem() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
@@ -463,15 +475,15 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
   for (int i = 0; i < NB; ++i) dzb[i] = 0.f;
 
   prefetch(first_token(0));
-  // the first step's inputs (no stores are in flight yet)
-  wait_vmem<0>();
   for (int kstep = 0; kstep < nsteps; ++kstep) {
     const int64_t t0 = first_token(kstep);
-    // this step's runs: wait for its prefetch, issued before the previous
-    // step's NSTORE dQ stores (the counter retires in issue order, so at
-    // most NSTORE outstanding means the prefetch has landed), read them,
-    // then refill the stage
-    wait_vmem<FC::NSTORE>();
+    // this step's runs: wait for its prefetch, read them, then refill the
+    // stage.  The loads into LDS share the vector memory counter with the
+    // previous step's dQ stores, and nothing orders a load's retirement
+    // before a store issued after it, so only a zero count proves the
+    // stage has landed (the compiler emits the same full wait before any
+    // LDS read that a load into LDS may have written)
+    wait_vmem<0>();
     uint32_t pq[TT][RW], pg[TT][RW];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
@@ -552,7 +564,7 @@ void bwd_qds_kernel(const void* __restrict__ q, const void* __restrict__ dout, i
             const int c = CH * w + j + u;
             const float ph = run_val<DT_BF16>(pq[tt], c);
             const float zc = zf[RN::feature(g, c)];
-            o2[u] = (fmaf(-go, zc, acc[tt][c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
+            o2[u] = (fmaf(-go, zc, acc[tt][c >> 2][c & 3]) * rd) * dphi_of_phi(ph);
           }
           if constexpr (OT == DT_BF16) {
             ow[j >> 1] = pack_bf16(o2[0], o2[1]);
@@ -641,11 +653,20 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
   __shared__ u32x4 simg[IMG_WORDS + Z_WORDS];
   __shared__ float zf[D];
   constexpr int NW = 4;             // waves (tiles per step)
-  // token-major operands of a 32-token contraction: tiles 2*kap and
-  // 2*kap + 1 write the low and high halves of one 16-byte slot per lane,
-  // so a slot is one operand (one LDS read)
-  __shared__ u32x4 xa[NW / 2][NB][64];      // phi(q)/den of block i
-  __shared__ u32x4 xb[NW / 2][NB + 1][64];  // G of block j; block NB: -G.O (hi, lo)
+  // each wave's tile as it holds it, row-major (16 token rows of d bf16
+  // values: phi(q)/den in rowq, G in rowg); the contraction reads them back
+  // token-major with the transposing LDS read.  The 16-byte chunks of a
+  // row are XOR-swizzled by the row (tile_slot), so that the four rows one
+  // 16-lane block reads lie in distinct banks.  xz: -G.O (hi, lo) of each
+  // token in columns 0 and 1, token-major; tiles 2*kap and 2*kap + 1 fill
+  // the low and high halves of a lane's 16-byte slot
+  constexpr int RC = D * 2 / 16;    // 16-byte chunks per row
+  __shared__ u32x4 rowq[NW][16 * RC];
+  __shared__ u32x4 rowg[NW][16 * RC];
+  __shared__ u32x4 xz[NW / 2][64];
+  auto tile_slot = [](int row, int chunk) {
+    return row * RC + (chunk ^ (2 * (row & 3) + 8 * ((row >> 2) & 1)));
+  };
   const u32x4* zimg = simg + IMG_WORDS;
 
   const int bh = blockIdx.y;
@@ -734,14 +755,11 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
                        s == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : dacc);
       dacc = mfma_bf16(as_bf16x8(zimg[(s * 2 + 1) * 64 + lane]), bt, dacc);
     }
-    // token-major G of this tile into LDS
+    // this tile's G rows into LDS: chunk w of the lane's run is the row's
+    // 16-byte chunk 4w + g
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s0 = j >> 1;
-      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{pg[4 * s0], pg[4 * s0 + 1], pg[4 * s0 + 2], pg[4 * s0 + 3]}),
-                                 sel[j & 1], f32x4{0.f, 0.f, 0.f, 0.f});
-      ((u32x2*)&xb[wave >> 1][j][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
-    }
+    for (int w = 0; w < NCH; ++w)
+      rowg[wave][tile_slot(n, 4 * w + g)] = u32x4{pg[4 * w], pg[4 * w + 1], pg[4 * w + 2], pg[4 * w + 3]};
     const bool ok = tb + n < N;
     const double rden = 1.0 / (double)dacc[0];
     const float rd = ok ? (float)rden : 0.f;  // zero past the end: no dS, dz share
@@ -761,7 +779,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       const float hi = bf16f(to_bf16(-go));
       const uint32_t w0 = g == 0 ? pack_bf16(hi, -go - hi) : 0u;
       const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{w0, 0u, 0u, 0u}), sel[0], f32x4{0.f, 0.f, 0.f, 0.f});
-      ((u32x2*)&xb[wave >> 1][NB][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+      ((u32x2*)&xz[wave >> 1][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
     }
     // dQ
     char* orow = oh + tb * orow_bytes + ooff;
@@ -775,7 +793,7 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
         for (int u = 0; u < 2; ++u) {
           const int c = CH * w + j + u;
           const float ph = run_val<DT_BF16>(pq, c);
-          o2[u] = (fmaf(-go, zf[RN::feature(g, c)], acc[c >> 2][c & 3]) * rd) * fminf(ph, 1.0f);
+          o2[u] = (fmaf(-go, zf[RN::feature(g, c)], acc[c >> 2][c & 3]) * rd) * dphi_of_phi(ph);
         }
         if constexpr (OT == DT_BF16) {
           ow[j >> 1] = pack_bf16(o2[0], o2[1]);
@@ -786,41 +804,52 @@ void bwd_qds4_kernel(const void* __restrict__ q, const void* __restrict__ dout, 
       }
       if (ok) store_words<OCB>(orow + w * 4 * OCB, ow);
     }
-    // token-major phi(q)/den into LDS
+    // this tile's phi(q)/den rows into LDS (bf16, as the contraction
+    // takes them)
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int s0 = i >> 1;
+    for (int w = 0; w < NCH; ++w) {
       uint32_t wa[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const uint32_t w = pq[4 * s0 + kk];
-        wa[kk] = pack_bf16(bf16lo(w) * rd, bf16hi(w) * rd);
+        const uint32_t x = pq[4 * w + kk];
+        wa[kk] = pack_bf16(bf16lo(x) * rd, bf16hi(x) * rd);
       }
-      const f32x4 tr = mfma_bf16(as_bf16x8(u32x4{wa[0], wa[1], wa[2], wa[3]}), sel[i & 1],
-                                 f32x4{0.f, 0.f, 0.f, 0.f});
-      ((u32x2*)&xa[wave >> 1][i][lane])[wave & 1] = u32x2{pack_bf16(tr[0], tr[1]), pack_bf16(tr[2], tr[3])};
+      rowq[wave][tile_slot(n, 4 * w + g)] = u32x4{wa[0], wa[1], wa[2], wa[3]};
     }
     __syncthreads();
     // the wave's dS patch (and dz columns) over the step's tiles: tiles
     // (2k, 2k + 1) make one 32-token contraction
+    // operand of feature block f of the tile pair: lane (g, m) addresses
+    // row 4g + (m >> 2), features 16f + 4 (m & 3) .. + 3 of each tile, and
+    // receives tokens 4g .. 4g + 3 of feature 16f + m: of tile 2 kap as
+    // elements 0..3, of tile 2 kap + 1 as elements 4..7 (the token order
+    // of xz)
+    const int rrow = 4 * g + (n >> 2);
+    auto operand = [&](const u32x4 (*t)[16 * RC], int kap, int f) {
+      const int slot = tile_slot(rrow, 2 * f + ((n & 3) >> 1));
+      const int half = (n & 1) * 8;
+      const u32x2 lo = lds_read_tr16((const char*)&t[2 * kap][slot] + half);
+      const u32x2 hi = lds_read_tr16((const char*)&t[2 * kap + 1][slot] + half);
+      return as_bf16x8(u32x4{lo[0], lo[1], hi[0], hi[1]});
+    };
 #pragma unroll
     for (int kap = 0; kap < NW / 2; ++kap) {
       bf16x8 aa[IW];
 #pragma unroll
-      for (int ii = 0; ii < IW; ++ii) aa[ii] = as_bf16x8(xa[kap][i0 + ii][lane]);
+      for (int ii = 0; ii < IW; ++ii) aa[ii] = operand(rowq, kap, i0 + ii);
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) {
-        const bf16x8 bb = as_bf16x8(xb[kap][j0 + jj][lane]);
+        const bf16x8 bb = operand(rowg, kap, j0 + jj);
 #pragma unroll
         for (int ii = 0; ii < IW; ++ii) ds[ii][jj] = mfma_bf16(aa[ii], bb, ds[ii][jj]);
       }
       if (has_dz) {
-        const bf16x8 bz = as_bf16x8(xb[kap][NB][lane]);
+        const bf16x8 bz = as_bf16x8(xz[kap][lane]);
 #pragma unroll
         for (int ii = 0; ii < IW; ++ii) dzb[ii] = mfma_bf16(aa[ii], bz, dzb[ii]);
       }
     }
-    __syncthreads();  // before the next step rewrites xa, xb
+    __syncthreads();  // before the next step rewrites rowq, rowg, xz
   };
 
   // two register sets in turn: the next step's inputs are in flight while
@@ -892,10 +921,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   if (DO_K) stage_image(nimg, head + IC::img_bytes(DT) / 16, ONE, DT == DT_BF16);
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int g = lane >> 4, n = lane & 15;
-  double dzr[DO_K ? Q4 : 1];
+  // dz is added in FP32 for bf16 inputs (their dS operands are bf16 hi
+  // parts, whose rounding is some 2^15 times that of dz to FP32) and in
+  // FP64 for fp32 inputs
+  using DzT = typename std::conditional<DT == DT_BF16, float, double>::type;
+  DzT dzr[DO_K ? Q4 : 1];
   if constexpr (DO_K) {
 #pragma unroll
-    for (int c = 0; c < Q4; ++c) dzr[c] = dz64[(int64_t)bh * D + Run<D, DT>::feature(g, c)];
+    for (int c = 0; c < Q4; ++c) dzr[c] = (DzT)dz64[(int64_t)bh * D + Run<D, DT>::feature(g, c)];
   }
   __syncthreads();
 
@@ -989,8 +1022,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int c = 4 * i + r;
-              const float dphi_c = fminf(run_val<DT>(pk[tt], c), 1.0f);
-              out[c] = (float)((double)acc[tt][i][r] + dzr[c]) * dphi_c;
+              const float dphi_c = dphi_of_phi(run_val<DT>(pk[tt], c));
+              out[c] = (float)((DzT)acc[tt][i][r] + dzr[c]) * dphi_c;
             }
           store_run<D, DT, OT>((char*)dk + out_head + t * osn * OES, out);
         }
@@ -1006,8 +1039,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 }
 
 // ---------------------------------------------------------------------------
+// Each step's launch status is taken as soon as it is known: the
+// launchers of the combine and the summary read (and so clear) the
+// runtime's last error, which would otherwise hide an earlier failure.
 template <int DT, int OT, int D>
-static void launch_rows(const BwdArgs& a) {
+static hipError_t launch_rows(const BwdArgs& a) {
+  hipError_t e = hipSuccess;
   const int BH = (int)(a.B * a.H);
   dim3 grid((unsigned)((a.N + a.Ta - 1) / a.Ta), BH);
   if constexpr (DT == DT_BF16 && D == 128) {
@@ -1017,7 +1054,8 @@ static void launch_rows(const BwdArgs& a) {
     bwd_qds4_kernel<OT><<<fgrid, 256, 0, a.stream>>>(
         a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
         a.img, a.z64, a.part);
-    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
   } else if constexpr (DT == DT_BF16 && (D == 32 || D == 64)) {
     // one pass: dQ and the per-wave partials of dS, dz (at d = 128 the
     // whole partial dS plus the query pass's state exceed the registers of
@@ -1027,7 +1065,8 @@ static void launch_rows(const BwdArgs& a) {
     bwd_qds_kernel<OT, D><<<fgrid, 256, 0, a.stream>>>(
         a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.P, a.Tw,
         a.img, a.z64, a.part);
-    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_BLOCKS, a.stream);
   } else {
     {
       ProfScope prof("bwd_query", a.stream);
@@ -1035,10 +1074,13 @@ static void launch_rows(const BwdArgs& a) {
           a.q, a.dout, a.sb, a.sh, a.sn, a.dq, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Ta, a.img,
           a.z64, a.stash);
     }
-    launch_summary(MODE_BWD, DT, D, a.q, a.dout, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
-                   a.stash, a.part, a.stream);
-    launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_SUMMARY, a.stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_summary(MODE_BWD, DT, D, a.q, a.dout, a.sb, a.sh, a.sn, a.B, a.H, a.N, a.P, a.Tw,
+                       a.stash, a.part, a.stream);
+    if (e != hipSuccess) return e;
+    e = launch_combine(a.part, a.P, a.dS64, a.dz64, a.dimg, DT, BH, D, PART_SUMMARY, a.stream);
   }
+  if (e != hipSuccess) return e;
   // both dS images fit in LDS except fp32 at d = 128 (2 x 64 KB): two passes
   ProfScope prof("bwd_key", a.stream);
   const dim3 kgrid((unsigned)a.Gk, BH);
@@ -1054,17 +1096,17 @@ static void launch_rows(const BwdArgs& a) {
         a.k, a.v, a.sb, a.sh, a.sn, a.dk, a.dv, a.osb, a.osh, a.osn, (int)a.H, a.N, a.Gk,
         a.dimg, a.dz64);
   }
+  return hipGetLastError();
 }
 
 template <int D>
 static hipError_t launch_backward_d(const BwdArgs& a) {
   hipError_t e = launch_images(a.S64, a.z64, a.img, a.in_dt, a.B * a.H, D, a.stream);
   if (e != hipSuccess) return e;
-  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) launch_rows<DT_BF16, DT_BF16, D>(a);
-  else if (a.in_dt == DT_BF16) launch_rows<DT_BF16, DT_FP32, D>(a);
-  else if (a.out_dt == DT_BF16) launch_rows<DT_FP32, DT_BF16, D>(a);
-  else launch_rows<DT_FP32, DT_FP32, D>(a);
-  return hipGetLastError();
+  if (a.in_dt == DT_BF16 && a.out_dt == DT_BF16) return launch_rows<DT_BF16, DT_BF16, D>(a);
+  if (a.in_dt == DT_BF16) return launch_rows<DT_BF16, DT_FP32, D>(a);
+  if (a.out_dt == DT_BF16) return launch_rows<DT_FP32, DT_BF16, D>(a);
+  return launch_rows<DT_FP32, DT_FP32, D>(a);
 }
 
 hipError_t launch_backward(const BwdArgs& a) {

@@ -59,6 +59,14 @@ __device__ __forceinline__ float dphi(float x) {
   else return x > 0.0f ? 1.0f : expf(x);
 }
 
+// phi'(x) from phi(x): min(phi, 1) (phi = x + 1 > 1 for x > 0, and
+// phi = exp(x) <= 1 = phi' otherwise).  phi >= 0, and non-negative floats
+// order as their bit patterns do as unsigned integers, so one integer min
+// gives it (fminf would canonicalise its operand first: two instructions).
+__device__ __forceinline__ float dphi_of_phi(float ph) {
+  return __uint_as_float(min(__float_as_uint(ph), 0x3f800000u));
+}
+
 __device__ __forceinline__ f32x4 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
