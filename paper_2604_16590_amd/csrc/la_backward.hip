@@ -937,6 +937,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   const char* vbase = (const char*)v + in_head;
   const int64_t out_head = (b * osb + h * osh) * OES + (int64_t)g * Run<D, DT>::CH * OES;
 
+  // (rows past the head's end are zero-filled; reading the last row again
+  // instead saves the fill but measured 1.5 % slower at d = 128)
   auto load_one = [&](int64_t t0, uint32_t* kw, uint32_t* vw) {
     const int64_t t = t0 + n;
     if (t < N) {

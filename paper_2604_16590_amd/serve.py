@@ -328,25 +328,34 @@ def run_reuse_loop(server, steps=80, members=1, H=16, N=262144, d=64, seed=7, ca
             "tokens_per_s": members * N * len(lat) / (sum(lat) * 1e-3) if lat else None}
 
 
-def bench_summary(budget_gb=200, n_requests=200, attention_only=True):
+def bench_summary(budget_gb=200, n_requests=200, attention_only=True, log=None):
     """Serving measurement for the benchmark: the literal 200 req/s Poisson
     stream (saturating; a bounded window of `n_requests` arrivals) and a
     point at 0.7x the measured saturated throughput, with server-generated
     inputs (the generator stands in for the upstream projection); then the
     same two points with caller-owned inputs from an InputPool, where the
     device time is attention only.  With 200 requests per point the p99
-    sits above two samples rather than being the maximum."""
+    sits above two samples rather than being the maximum.  `log`, if
+    given, is called with a line after each point."""
     import torch
+    say = log or (lambda line: None)
+
+    def point(name, res):
+        say("serving %s: %.1f req/s, p50 %.1f ms, p99 %.1f ms" % (
+            name, res["req_per_s"] or 0.0, res["p50_ms"] or 0.0, res["p99_ms"] or 0.0))
+        return res
+
     with Server(int(budget_gb * 1e9), max_slots=4, n_streams=4, max_slices_per_request=2) as srv:
-        sat = run_poisson(srv, n_requests, 200.0, seed=5)
+        sat = point("generated, saturated", run_poisson(srv, n_requests, 200.0, seed=5))
         cap = sat["req_per_s"] or 1.0
-        sub = run_poisson(srv, n_requests, 0.7 * cap, seed=6)
+        sub = point("generated, 0.7x", run_poisson(srv, n_requests, 0.7 * cap, seed=6))
         c = srv.stats()
         peak = c.peak_bytes_in_use
         # diffusion loops reusing one summary: one member, and a whole
         # 64-member ensemble request (N = 262,144 tokens, H16 d64)
         loop1 = run_reuse_loop(srv, members=1)
         loop64 = run_reuse_loop(srv, members=64)
+        say("serving reuse loops done")
     out = {"workload": "Poisson arrivals, N log-uniform [4096, 1048576], 64 members, "
                        "H16 d64 bf16, server-generated N(0,1) inputs, budget %d GB" % budget_gb,
            "saturated_200rps": sat, "sub_saturation": sub,
@@ -361,9 +370,11 @@ def bench_summary(budget_gb=200, n_requests=200, attention_only=True):
         try:
             # the arena holds only workspaces and the kept S, z here
             with Server(16 << 30, max_slots=4, n_streams=4, max_slices_per_request=2) as srv:
-                a_sat = run_poisson(srv, n_requests, 200.0, seed=5, pool=pool)
+                a_sat = point("attention only, saturated",
+                              run_poisson(srv, n_requests, 200.0, seed=5, pool=pool))
                 a_cap = a_sat["req_per_s"] or 1.0
-                a_sub = run_poisson(srv, n_requests, 0.7 * a_cap, seed=6, pool=pool)
+                a_sub = point("attention only, 0.7x",
+                              run_poisson(srv, n_requests, 0.7 * a_cap, seed=6, pool=pool))
                 a_loop64 = run_reuse_loop(srv, members=64, pool=pool)
         finally:
             pool.free()
