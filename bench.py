@@ -158,10 +158,16 @@ def kernel_table(stats, steps, elems, esize):
     return out
 
 
+# the sources the long-context step's kernels and their launch choices are
+# built from (the counter figures go stale when any of these changes)
+STEP_SOURCES = ("la_api.cpp", "la_backward.hip", "la_device.h", "la_forward.hip",
+                "la_kernels.h", "la_profile.cpp", "la_profile.h", "la_summary.h")
+
+
 def source_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2604_16590_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in STEP_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -473,13 +479,13 @@ def counter_means(directory, counter):
     return {k: (sum(v) / len(v), len(v)) for k, v in out.items()}
 
 
-def summarize_profiles(top):
+def summarize_profiles(top, prof=None):
     """profiles/kernel_stats_long_context_bf16.txt from a --kernel-trace
     --stats run and profiles/counters_long_context_bf16.{json,txt} from
     FETCH_SIZE and WRITE_SIZE runs, each scaled by what the counter reads
     for the library's plain 1 GiB copy.  The commands are the ones in
     the headers below (run from /tmp with TMPDIR=/tmp)."""
-    prof = os.path.join(ROOT, "profiles")
+    prof = prof or os.path.join(ROOT, "profiles")
     cmd = ("rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py "
            "--steps 5 --warmup 2 --no-fp32 --no-cpu-baseline --no-serve --no-others")
     cal = "rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py --copy-calibration"
@@ -491,11 +497,20 @@ def summarize_profiles(top):
                                                           "/root/repo/gpurun_out/prof/trace"),
              "# 2 warm-up + 5 timed steps, then 1 warm-up and 5 forward-only steps inside bench.py;",
              "# kernel = the name bench.py reports (its HIP-event averages cover the same launches)",
-             "%-14s %-60s %6s %14s %12s %7s" % ("kernel", "name", "calls", "total_ns", "avg_ns", "pct")]
+             "# bench_avg_ns: the same kernel's average over the timed steps by the bench's own "
+             "HIP events in this run",
+             "%-14s %-60s %6s %14s %12s %7s %13s" % ("kernel", "name", "calls", "total_ns", "avg_ns",
+                                                    "pct", "bench_avg_ns")]
+    events = {}
+    trace_out = os.path.join(top, "trace.out")
+    if os.path.isfile(trace_out):
+        events = {k: v["avg_ms"] * 1e6 for k, v in last_json_line(trace_out)["kernels"].items()}
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        lines.append("%-14s %-60s %6s %14s %12.0f %7.2f" % (
-            profile_name(r["Name"]) or "-", r["Name"][:60], r["Calls"], r["TotalDurationNs"],
-            float(r["AverageNs"]), float(r["Percentage"])))
+        pname = profile_name(r["Name"])
+        ev = events.get(pname if pname != "combine_bwd" else "", None)
+        lines.append("%-14s %-60s %6s %14s %12.0f %7.2f %13s" % (
+            pname or "-", r["Name"][:60], r["Calls"], r["TotalDurationNs"],
+            float(r["AverageNs"]), float(r["Percentage"]), "%.0f" % ev if ev else "-"))
     with open(os.path.join(prof, "kernel_stats_long_context_bf16.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     # HBM traffic
@@ -551,7 +566,100 @@ def summarize_profiles(top):
                 k["alg_bytes_per_launch"] / 1e9))
     with open(os.path.join(prof, "counters_long_context_bf16.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    avg_ms = {profile_name(r["Name"]): float(r["AverageNs"]) / 1e6 for r in rows
+              if profile_name(r["Name"])}
+    if os.path.isdir(os.path.join(top, "mfma")):
+        summarize_mfma(os.path.join(top, "mfma"), prof, cmd, avg_ms)
+    if os.path.isfile(os.path.join(top, "bench.json")):
+        summarize_bench(os.path.join(top, "bench.json"), prof)
+    if os.path.isfile(os.path.join(top, "serve2000.json")):
+        summarize_serving(os.path.join(top, "serve2000.json"), prof)
     print("wrote profiles/ summaries (source digest %s)" % rec["source_digest"])
+
+
+MFMA_COUNTERS = "SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES"
+
+
+def summarize_mfma(directory, prof, cmd, avg_ms):
+    """Matrix-core work per launch (SQ_INSTS_VALU_MFMA_MOPS_BF16 counts bf16
+    matrix-core work in units of 512 FLOPs over the chip), over the
+    kernel's average duration from the kernel trace."""
+    mops = counter_means(directory, "SQ_INSTS_VALU_MFMA_MOPS_BF16")
+    lines = ["# matrix-core work per launch from rocprofv3 counters: long-context workload, bf16 "
+             "fwd+bwd",
+             "# command: cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc " + MFMA_COUNTERS,
+                                                          "/root/repo/gpurun_out/prof/mfma"),
+             "# SQ_INSTS_VALU_MFMA_MOPS_BF16 counts bf16 matrix-core work in units of 512 FLOPs "
+             "(summed over the chip);",
+             "# TFLOP/s uses the kernel's average duration from kernel_stats_long_context_bf16.txt; "
+             "peak 2500 TFLOP/s dense bf16",
+             "%-14s %14s %12s %10s %10s %14s" % ("kernel", "MOPS/launch", "TFLOP/launch", "avg_ms",
+                                                "TFLOP/s", "frac_of_2.5PF")]
+    by = {}
+    for name, (v, _) in mops.items():
+        pname = profile_name(name)
+        if pname:
+            by[pname] = v
+    for _, pname in PROFILE_KERNELS:
+        if pname in by and pname in avg_ms:
+            tf = by[pname] * 512 / 1e12
+            rate = tf / (avg_ms[pname] * 1e-3)
+            lines.append("%-14s %14.4g %12.4f %10.4f %10.1f %14.4f" % (
+                pname, by[pname], tf, avg_ms[pname], rate, rate / 2500.0))
+    with open(os.path.join(prof, "mfma_long_context_bf16.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def last_json_line(path):
+    with open(path) as f:
+        return json.loads([l for l in f if l.startswith("{")][-1])
+
+
+def summarize_bench(path, prof):
+    """The bench line of a default run, with its headline figures first."""
+    j = last_json_line(path)
+    lines = ["# bench.py on one MI355X: long-context workload, bf16 fwd+bwd (plus bf16 forward, "
+             "fp32 fwd+bwd, other shapes, serving, oracle on the host)",
+             "# command: python bench.py   (20 timed steps after 3 warm-up; per-kernel times from "
+             "the library's HIP-event timer)",
+             "value %.1f tokens/s, %.3f ms/step; forward alone %.1f tokens/s (%.3f ms)" % (
+                 j["value"], j["ms_per_step"], j["fwd_tokens_per_s"], j["fwd_ms"]),
+             "roofline: " + json.dumps(j["roofline"]),
+             "%-14s %8s %10s %8s %8s" % ("kernel", "launches", "avg_ms", "alg_GB", "GB_s")]
+    for name, k in j["kernels"].items():
+        lines.append("%-14s %8.1f %10.4f %8s %8s" % (name, k["launches_per_step"], k["avg_ms"],
+                                                     k.get("alg_GB", "-"), k.get("GB_s", "-")))
+    for key in ("fp32", "cpu_baseline", "errors_vs_oracle_on_sample"):
+        lines.append("%s: %s" % (key, json.dumps(j.get(key))))
+    lines += ["# full JSON line", json.dumps(j)]
+    with open(os.path.join(prof, "bench_long_context_bf16.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_serving(path, prof):
+    """The serving block of a run with --serve-window 2000."""
+    j = last_json_line(path)
+    sv = j["serve"]
+    lines = ["# serving, 2,000 Poisson arrivals per point: 64-member requests, N log-uniform "
+             "[4096, 1048576], H16 d64 bf16",
+             "# command: python bench.py --serve-window 2000 --no-fp32 --no-others "
+             "--no-cpu-baseline",
+             "%-34s %8s %10s %10s %10s %12s %10s" % ("point", "req/s", "p50_ms", "p99_ms",
+                                                    "p999_ms", "Mtok/s", "attn_TB/s")]
+
+    def row(name, r):
+        return "%-34s %8.2f %10.1f %10.1f %10.1f %12.1f %10.3f" % (
+            name, r["req_per_s"], r["p50_ms"], r["p99_ms"], r["p999_ms"], r["tokens_per_s"] / 1e6,
+            r.get("attention_TB_s") or 0.0)
+    lines.append(row("generated inputs, 200 req/s", sv["saturated_200rps"]))
+    lines.append(row("generated inputs, 0.7x capacity", sv["sub_saturation"]))
+    ao = sv.get("attention_only")
+    if ao:
+        lines.append(row("caller-owned inputs, 200 req/s", ao["saturated_200rps"]))
+        lines.append(row("caller-owned inputs, 0.7x capacity", ao["sub_saturation"]))
+    lines += ["# full serve block", json.dumps(sv)]
+    with open(os.path.join(prof, "serving_poisson_2000_arrivals.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():

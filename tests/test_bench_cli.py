@@ -1,5 +1,6 @@
 """bench.py's command line on the CPU: it measures one GPU only and says so
 for any other count, before touching a device."""
+import json
 import os
 import subprocess
 import sys
@@ -38,3 +39,62 @@ def test_matrix_core_flops_follow_each_path_operands():
     assert bench.mma_flops_per_step(fp32_step, "fp32", 1, 128) == 6 * unit(128)
     # combine and the image builder do no products of the method
     assert bench.mma_flops_per_step({"combine": {"launches_per_step": 2.0}}, "bf16", 1, 128) == 0
+
+
+def _write_csv(path, header, rows):
+    import csv
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+COUNTER_HEADER = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id",
+                  "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size",
+                  "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Counter_Name",
+                  "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+KEY = "void la::bwd_key_kernel<0, 0, 128, 3>(void const*, ...)"
+COPY = "void (anonymous namespace)::stream_copy_swept_kernel<8, true>(...)"
+
+
+def _counter_rows(counter, per_kernel):
+    rows, i = [], 1
+    for name, values in per_kernel:
+        for v in values:
+            rows.append([i, i, "Agent 1", 1, 1, 1, 1, 1, name, 256, 0, 0, 1, 0, 1, counter, v, 0, 1])
+            i += 1
+    return rows
+
+
+def test_profile_summaries_from_rocprof_csv(tmp_path):
+    # rocprofv3 output in the layout the GPU runs write: the summarizer
+    # scales each kernel's mean counter per dispatch by the copy
+    # calibration and records the current source digest
+    import bench
+    top = tmp_path / "prof"
+    _write_csv(str(top / "trace" / "run_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs",
+                "StdDev"],
+               [[KEY, 2, 6000000, 3000000.0, 90.0, 1, 1, 0], [COPY, 1, 600000, 600000.0, 10.0, 1, 1, 0]])
+    _write_csv(str(top / "fetch" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("FETCH_SIZE", [(KEY, [100.0, 300.0])]))
+    _write_csv(str(top / "write" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("WRITE_SIZE", [(KEY, [50.0, 50.0])]))
+    # the calibration copy moves 1 GiB each way: FETCH_SIZE reads half of it
+    _write_csv(str(top / "copy_fetch" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("FETCH_SIZE", [(COPY, [524288.0, 524288.0])]))
+    _write_csv(str(top / "copy_write" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("WRITE_SIZE", [(COPY, [1048576.0])]))
+    out = tmp_path / "profiles"
+    out.mkdir()
+    bench.summarize_profiles(str(top), str(out))
+    rec = json.load(open(out / "counters_long_context_bf16.json"))
+    assert rec["source_digest"] == bench.source_digest()
+    assert rec["copy_factor_fetch"] == 2.0 and rec["copy_factor_write"] == 1.0
+    k = rec["kernels"]["bwd_key"]
+    assert k["fetch_kib"] == 200.0 and k["write_kib"] == 50.0 and k["dispatches"] == 2
+    assert k["hbm_bytes_per_launch"] == (200.0 * 2 + 50.0) * 1024
+    assert k["alg_bytes_per_launch"] == 4 * 8 * 2097152 * 128 * 2
+    stats = open(out / "kernel_stats_long_context_bf16.txt").read()
+    assert "bwd_key" in stats and "3000000" in stats
