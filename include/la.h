@@ -266,8 +266,11 @@ la_status la_tile_blend(const la_tile_desc* desc, const void* tiles, void* field
  * pass 2 reads Q once and writes O once.  Requirements beyond
  * la_tile_desc's: dtype LA_BF16, d = C / heads in {16, 32, 64},
  * 2 * halo <= core in every dimension (then each position lies in at most
- * two tiles per dimension) and at most 65,536 tokens per extended tile;
- * otherwise LA_ERR_UNSUPPORTED.
+ * two tiles per dimension), at most 65,536 tokens per extended tile and
+ * fewer than 2^31 tokens per field; otherwise LA_ERR_UNSUPPORTED.  The
+ * Hann weights use the hardware sine and the divisions by den and by the
+ * weight sum the hardware reciprocal (about 1e-6 relative, far below the
+ * bf16 rounding of o).
  * ws: ws_bytes >= la_tiled_workspace_size(desc, heads), 256-byte aligned.
  */
 la_status la_tiled_workspace_size(const la_tile_desc* desc, int64_t heads, size_t* bytes);

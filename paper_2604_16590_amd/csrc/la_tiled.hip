@@ -46,16 +46,18 @@ struct TGeo {
   int P, Tw;         // partials per (tile, head), tokens per partial
 };
 
-__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t hi) {
-  return v < 0 ? 0 : (v > hi ? hi : v);
+__device__ __forceinline__ uint32_t clamp32(int32_t v, int32_t hi) {
+  return (uint32_t)min(max(v, 0), hi);
 }
 
 // Hann weight of coordinate u of a tile extent L (cell centres, strictly
 // positive on [0, L)): sin^2(pi (u + 1/2) / L); zero outside the tile.
-__device__ __forceinline__ float hann_w(int64_t u, int64_t L) {
-  if (u < 0 || u >= L) return 0.f;
-  const float s = sinpif(((float)u + 0.5f) / (float)L);
-  return s * s;
+// w(u) = sin^2(pi (u + 1/2) / L) for 0 <= u < L, else 0; inv2L = 1 / (2L).
+// The hardware sine takes its argument in revolutions (sin(2 pi x)); its
+// error (about 1e-6) is far below the bf16 rounding of the blended output.
+__device__ __forceinline__ float hann_w(int32_t u, int32_t L, float inv2L) {
+  const float s = __builtin_amdgcn_sinf(((float)u + 0.5f) * inv2L);
+  return (u >= 0 && u < L) ? s * s : 0.f;
 }
 
 // Operands of one (tile, head) for the apply pass, in the matrix cores'
@@ -66,9 +68,15 @@ struct TiledCfg {
   using IC = ImageCfg<D>;
   static constexpr int NT = D / 16, NS = IC::NS, Q4 = D / 4;
   static constexpr int S_WORDS = NT * NS * 64;  // S^T hi parts
-  static constexpr int Z_WORDS = NS * 2 * 64;   // z tile, hi + lo
+  // z tile: one operand per k-step whose even rows hold z's bf16 hi parts
+  // and odd rows its lo parts, so output rows 4g and 4g + 1 of a product
+  // are the hi and lo parts of den in the same lane
+  static constexpr int Z_WORDS = NS * 64;
   static constexpr int SLOT = S_WORDS + Z_WORDS;
-  static constexpr int WAVES = 8, TT = 2;
+  // four waves per apply workgroup: two workgroups share a compute unit
+  // (the eight slots take 80 KiB of LDS at d = 64), so one's staging
+  // overlaps the other's streaming (3.75 -> 3.29 ms against eight waves)
+  static constexpr int WAVES = 4, TT = 2;
   static constexpr int QW = Q4 * 2 / 4;         // words of a lane's query run
 };
 
@@ -78,7 +86,9 @@ struct TiledCfg {
 // workgroup per (tile, head); wave w sums tokens [w*Tw, w*Tw + Tw) in FP32
 // (Tw <= 16,384), the four partials are added in FP64 in a fixed order
 // through LDS, and the result is written as the apply's operand slot.
-// grid: x = tile, y = head.
+// grid: one workgroup per (tile, head), head fastest: the H workgroups of
+// a tile run side by side and together read whole token rows (each reads
+// only its head's d features of a row).
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
@@ -93,9 +103,9 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
   __shared__ __align__(16) float red[4][E];
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int gq = lane >> 4, m = lane & 15;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = blockIdx.x / g.H;
   const int p = wave;
-  const int64_t head = blockIdx.y;
+  const int64_t head = blockIdx.x % g.H;
   const int64_t t_begin = (int64_t)p * g.Tw;
   const int64_t t_end = min(g.tile_tokens, t_begin + (int64_t)g.Tw);
   float* out = red[p];
@@ -118,19 +128,28 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
     const uint32_t neg_inf = 0xff80ff80u;
     uint32_t* xch = nullptr;
     // the step at t0: lane group gq takes tokens t0 + R*gq + r; decompose
-    // the first one, then walk in (ut, uy, ux) order
+    // the first one, then walk in (ut, uy, ux) order.  32-bit throughout
+    // (an extended tile holds at most 65,536 tokens, the field fewer than
+    // 2^31), so the walk costs a few instructions per token
+    const uint32_t L1 = (uint32_t)g.L[1], L2 = (uint32_t)g.L[2], L12 = L1 * L2;
+    const int32_t O0 = (int32_t)o0, O1 = (int32_t)o1, O2 = (int32_t)o2;
+    const int32_t M0 = (int32_t)g.dims[0] - 1, M1 = (int32_t)g.dims[1] - 1,
+                  M2 = (int32_t)g.dims[2] - 1;
+    const uint32_t N1 = (uint32_t)g.dims[1], N2 = (uint32_t)g.dims[2];
+    const uint32_t tend = (uint32_t)t_end;
     auto load = [&](int64_t t0, SummaryRegs<DT_BF16, D, MODE_FWD>& x) {
-      int64_t j = t0 + R * gq;
-      int64_t ut = j / (g.L[1] * g.L[2]);
-      int64_t uy = (j / g.L[2]) % g.L[1];
-      int64_t ux = j % g.L[2];
+      const uint32_t j = (uint32_t)t0 + R * gq;
+      uint32_t ut = j / L12;
+      const uint32_t rem = j - ut * L12;
+      uint32_t uy = rem / L2;
+      uint32_t ux = rem - uy * L2;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (j + r < t_end) {
-          const int64_t gt = clamp64(o0 + ut, g.dims[0] - 1);
-          const int64_t gy = clamp64(o1 + uy, g.dims[1] - 1);
-          const int64_t gx = clamp64(o2 + ux, g.dims[2] - 1);
-          const int64_t off = ((gt * g.dims[1] + gy) * g.dims[2] + gx) * rowb;
+        if (j + r < tend) {
+          const uint32_t gt = clamp32(O0 + (int32_t)ut, M0);
+          const uint32_t gy = clamp32(O1 + (int32_t)uy, M1);
+          const uint32_t gx = clamp32(O2 + (int32_t)ux, M2);
+          const int64_t off = (int64_t)((gt * N1 + gy) * N2 + gx) * rowb;
           // plain loads: halo tokens are read again by the neighbouring
           // tiles, dispatched at about the same time
           load_words<C::KB>(kb + off, x.kw[r]);
@@ -180,7 +199,7 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
   // FP64 sum of the four partials, (p0 + p1) + (p2 + p3), element u of the
   // partial layout (tile (i, j), lane (g, n), register r: S[F(4g + r) + i][F n + j];
   // then z), into the operand slot: S^T hi parts at (row e, contraction c),
-  // z as hi and lo parts in all 16 rows of the z tile
+  // z's hi parts in the even rows of the z tile and its lo parts in the odd
   uint16_t* slot = (uint16_t*)(slots + (tile * g.H + head) * TC::SLOT);
   for (int u = threadIdx.x; u < E; u += 256) {
     const double sum = ((double)red[0][u] + (double)red[1][u]) + ((double)red[2][u] + (double)red[3][u]);
@@ -199,13 +218,9 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
       const uint16_t lo = to_bf16((float)(sum - (double)bf16f(hi)));
       const int kp = RB::pos(c);
       for (int mm = 0; mm < 16; ++mm) {
-        const int word = TC::S_WORDS + ((kp >> 3) * 2) * 64 + 16 * RB::group(c) + mm;
-        slot[word * 8 + (kp & 7)] = hi;
-        slot[(word + 64) * 8 + (kp & 7)] = lo;
-        if (TC::Q4 < 8) {
-          slot[word * 8 + (kp & 7) + 4] = 0;
-          slot[(word + 64) * 8 + (kp & 7) + 4] = 0;
-        }
+        const int word = TC::S_WORDS + (kp >> 3) * 64 + 16 * RB::group(c) + mm;
+        slot[word * 8 + (kp & 7)] = (mm & 1) ? lo : hi;
+        if (TC::Q4 < 8) slot[word * 8 + (kp & 7) + 4] = 0;
       }
     }
   }
@@ -217,12 +232,14 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
 // core / 2; its positions are covered only by tiles j - 1 and j of that
 // dimension (halo <= core / 2).  Slot s = (st, sy, sx) in {0, 1}^3 holds
 // tile (jt - 1 + st, jy - 1 + sy, jx - 1 + sx) if it exists: the S^T hi
-// parts (S_t to about 2^-9) and the hi + lo z tile.  Eight waves take the
-// cell's 16-token tiles (row-major over the cell) two at a time.
+// parts (S_t to about 2^-9) and the hi / lo z tile.  Eight waves take the
+// cell's 16-token tiles (row-major over the cell) two at a time.  The
+// eight slots take 80 KiB of LDS at d = 64, so two workgroups share a
+// compute unit and one's staging overlaps the other's streaming.
 // ---------------------------------------------------------------------------
 
 template <int D>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(64 * TiledCfg<D>::WAVES) __attribute__((amdgpu_waves_per_eu(2)))
 void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
                        const void* __restrict__ img) {
   using TC = TiledCfg<D>;
@@ -230,10 +247,10 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
   using RN = Run<D, DT_BF16>;
   constexpr int NT = TC::NT, NS = TC::NS, Q4 = TC::Q4, TT = TC::TT, QW = TC::QW;
   __shared__ u32x4 simg[8 * TC::SLOT];
-  __shared__ int valid[8];
 
-  const int64_t head = blockIdx.y;
-  const int64_t cell = blockIdx.x;
+  // one workgroup per (cell, head), head fastest (as the summary pass)
+  const int64_t head = blockIdx.x % g.H;
+  const int64_t cell = blockIdx.x / g.H;
   const int64_t jc[3] = {cell / (g.cells[1] * g.cells[2]), (cell / g.cells[2]) % g.cells[1],
                          cell % g.cells[2]};
   int64_t lo[3], ext[3];
@@ -252,84 +269,101 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
   const char* qh = (const char*)q + head * D * 2;
   char* oh = (char*)o + head * D * 2;
 
-  // per lane: token e of the cell -> grid position and its field offset
+  // per lane: token e of the cell -> grid position, field offset and the
+  // Hann weights of the (up to) two covering tiles per dimension.  32-bit
+  // coordinates (a cell holds fewer than 65,536 tokens, the field fewer
+  // than 2^31); the covering tiles' origins are the same for the whole
+  // workgroup (origin -1 << 30 marks a tile outside the grid: weight 0)
   struct Tok {
     int64_t off;
     float wt[2], wy[2], wx[2];
     bool ok;
   };
-  auto locate = [&](int64_t e) {
+  const uint32_t E1 = (uint32_t)ext[1], E2 = (uint32_t)ext[2], E12 = E1 * E2;
+  const uint32_t VOL = (uint32_t)vol;
+  const int32_t P0 = (int32_t)lo[0], P1 = (int32_t)lo[1], P2 = (int32_t)lo[2];
+  const uint32_t N1 = (uint32_t)g.dims[1], N2 = (uint32_t)g.dims[2];
+  int32_t org[3][2], Lk[3];
+  float inv2L[3];
+  for (int k = 0; k < 3; ++k) {
+    Lk[k] = (int32_t)g.L[k];
+    inv2L[k] = 0.5f / (float)g.L[k];
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      const int64_t tix = jc[k] - 1 + sidx;
+      org[k][sidx] = (tix >= 0 && tix < g.n[k]) ? (int32_t)(tix * g.core[k] - g.halo[k]) : -(1 << 30);
+    }
+  }
+  auto locate = [&](int64_t e64) {
     Tok t;
-    t.ok = e < vol;
-    const int64_t ee = t.ok ? e : vol - 1;
-    const int64_t p0 = lo[0] + ee / (ext[1] * ext[2]);
-    const int64_t p1 = lo[1] + (ee / ext[2]) % ext[1];
-    const int64_t p2 = lo[2] + ee % ext[2];
-    t.off = ((p0 * g.dims[1] + p1) * g.dims[2] + p2) * rowb;
-    const int64_t p[3] = {p0, p1, p2};
+    const uint32_t e = (uint32_t)e64;
+    t.ok = e64 < (int64_t)VOL;
+    const uint32_t ee = t.ok ? e : VOL - 1;
+    const uint32_t a0 = ee / E12, r0 = ee - a0 * E12;
+    const uint32_t a1 = r0 / E2, a2 = r0 - a1 * E2;
+    const int32_t p[3] = {P0 + (int32_t)a0, P1 + (int32_t)a1, P2 + (int32_t)a2};
+    t.off = (int64_t)(((uint32_t)p[0] * N1 + (uint32_t)p[1]) * N2 + (uint32_t)p[2]) * rowb;
     float* w[3] = {t.wt, t.wy, t.wx};
+#pragma unroll
     for (int k = 0; k < 3; ++k)
-      for (int sidx = 0; sidx < 2; ++sidx) {
-        const int64_t tix = jc[k] - 1 + sidx;
-        w[k][sidx] = (tix >= 0 && tix < g.n[k])
-                         ? hann_w(p[k] - (tix * g.core[k] - g.halo[k]), g.L[k]) : 0.f;
-      }
+#pragma unroll
+      for (int sidx = 0; sidx < 2; ++sidx) w[k][sidx] = hann_w(p[k] - org[k][sidx], Lk[k], inv2L[k]);
     return t;
   };
 
   const int64_t ntile = (vol + 15) / 16;
   const int64_t per_step = (int64_t)TC::WAVES * TT;
-  // the next step's queries are loaded while this step computes
-  Tok tkn[TT];
-  uint32_t qwn[TT][QW];
-  auto fetch = [&](int64_t base) {
-#pragma unroll
-    for (int u = 0; u < TT; ++u) {
-      tkn[u] = locate((base + u) * 16 + n);
-      load_run<D, DT_BF16>(qh + tkn[u].off + gl * RN::CB, qwn[u]);
-    }
-  };
-  if ((int64_t)wave * TT < ntile) fetch((int64_t)wave * TT);
-
-  // stage the covering tiles' operands (the first queries are in flight):
-  // every load of a thread is issued before its LDS stores
-  {
-    constexpr int PER = (8 * TC::SLOT + 511) / 512;  // words per thread
-    u32x4 buf[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int w = threadIdx.x + 512 * i;
-      const int s = w / TC::SLOT, ws = w % TC::SLOT;
-      const int64_t tt = jc[0] - 1 + (s >> 2), ty = jc[1] - 1 + ((s >> 1) & 1), tx = jc[2] - 1 + (s & 1);
-      const bool ok = w < 8 * TC::SLOT && tt >= 0 && tt < g.n[0] && ty >= 0 && ty < g.n[1] &&
-                      tx >= 0 && tx < g.n[2];
-      if (ok) buf[i] = ((const u32x4*)img)[(((tt * g.n[1] + ty) * g.n[2] + tx) * g.H + head) * TC::SLOT + ws];
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int w = threadIdx.x + 512 * i;
-      if (w < 8 * TC::SLOT) simg[w] = buf[i];  // slots of missing tiles are never read
-    }
-    if (threadIdx.x < 8) {
-      const int s = threadIdx.x;
-      const int64_t tt = jc[0] - 1 + (s >> 2), ty = jc[1] - 1 + ((s >> 1) & 1), tx = jc[2] - 1 + (s & 1);
-      valid[s] = tt >= 0 && tt < g.n[0] && ty >= 0 && ty < g.n[1] && tx >= 0 && tx < g.n[2];
-    }
-  }
-  __syncthreads();
-  int vmask = 0;
-  for (int s = 0; s < 8; ++s) vmask |= valid[s] ? (1 << s) : 0;
-
-  for (int64_t base = (int64_t)wave * TT; base < ntile; base += per_step) {
+  // two register sets in turn: a step's queries are loaded while the
+  // previous step computes
+  struct Step {
     Tok tk[TT];
     uint32_t qw[TT][QW];
+  };
+  auto fetch = [&](int64_t base, Step& x) {
 #pragma unroll
     for (int u = 0; u < TT; ++u) {
-      tk[u] = tkn[u];
-#pragma unroll
-      for (int w = 0; w < QW; ++w) qw[u][w] = qwn[u][w];
+      x.tk[u] = locate((base + u) * 16 + n);
+      load_run<D, DT_BF16>(qh + x.tk[u].off + gl * RN::CB, x.qw[u]);
     }
-    if (base + per_step < ntile) fetch(base + per_step);
+  };
+  Step sa, sb;
+  const int64_t base0 = (int64_t)wave * TT;
+  if (base0 < ntile) fetch(base0, sa);
+
+  // stage the covering tiles' operands (the first queries are in flight):
+  // every load of a thread is issued before its LDS stores (in two rounds
+  // of loads, then stores, to bound the registers held)
+  {
+    constexpr int NTH = 64 * TC::WAVES;
+    constexpr int PER = (8 * TC::SLOT + NTH - 1) / NTH;  // words per thread
+    constexpr int HALF = (PER + 1) / 2;
+#pragma unroll
+    for (int r0 = 0; r0 < PER; r0 += HALF) {
+      u32x4 buf[HALF];
+#pragma unroll
+      for (int i = 0; i < HALF; ++i) {
+        const int w = threadIdx.x + NTH * (r0 + i);
+        const int s = w / TC::SLOT, ws = w % TC::SLOT;
+        const int64_t tt = jc[0] - 1 + (s >> 2), ty = jc[1] - 1 + ((s >> 1) & 1), tx = jc[2] - 1 + (s & 1);
+        const bool ok = r0 + i < PER && w < 8 * TC::SLOT && tt >= 0 && tt < g.n[0] && ty >= 0 &&
+                        ty < g.n[1] && tx >= 0 && tx < g.n[2];
+        if (ok) buf[i] = ((const u32x4*)img)[(((tt * g.n[1] + ty) * g.n[2] + tx) * g.H + head) * TC::SLOT + ws];
+      }
+#pragma unroll
+      for (int i = 0; i < HALF; ++i) {
+        const int w = threadIdx.x + NTH * (r0 + i);
+        if (r0 + i < PER && w < 8 * TC::SLOT) simg[w] = buf[i];  // slots of missing tiles are never read
+      }
+    }
+  }
+  // the slots whose tile exists (the same for every thread)
+  int vmask = 0;
+  for (int s = 0; s < 8; ++s) {
+    const int64_t tt = jc[0] - 1 + (s >> 2), ty = jc[1] - 1 + ((s >> 1) & 1), tx = jc[2] - 1 + (s & 1);
+    if (tt >= 0 && tt < g.n[0] && ty >= 0 && ty < g.n[1] && tx >= 0 && tx < g.n[2]) vmask |= 1 << s;
+  }
+  __syncthreads();
+
+  auto compute = [&](const Step& x) {
     // phi(q) as matrix-core operands
     bf16x8 bq[TT][NS];
 #pragma unroll
@@ -340,8 +374,8 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
 #pragma unroll
         for (int pp = 0; pp < 4; ++pp) {
           const int c0 = 8 * s + 2 * pp;
-          w[pp] = c0 < Q4 ? pack_bf16(phi<DT_BF16>(word_elem<DT_BF16>(qw[u], c0)),
-                                      phi<DT_BF16>(word_elem<DT_BF16>(qw[u], c0 + 1)))
+          w[pp] = c0 < Q4 ? pack_bf16(phi<DT_BF16>(word_elem<DT_BF16>(x.qw[u], c0)),
+                                      phi<DT_BF16>(word_elem<DT_BF16>(x.qw[u], c0 + 1)))
                           : 0u;
         }
         bq[u][s] = as_bf16x8(w);
@@ -359,7 +393,7 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
       bool any = false;
 #pragma unroll
       for (int u = 0; u < TT; ++u) {
-        ws[u] = tk[u].ok ? tk[u].wt[s >> 2] * tk[u].wy[(s >> 1) & 1] * tk[u].wx[s & 1] : 0.f;
+        ws[u] = x.tk[u].ok ? x.tk[u].wt[s >> 2] * x.tk[u].wy[(s >> 1) & 1] * x.tk[u].wx[s & 1] : 0.f;
         any |= ws[u] > 0.f;
       }
       if (!__any(any)) continue;  // no token of these tiles in this slot's tile
@@ -377,18 +411,17 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
         }
 #pragma unroll
       for (int ks = 0; ks < NS; ++ks) {
-        const bf16x8 zh = as_bf16x8(zt[(ks * 2 + 0) * 64 + lane]);
-        const bf16x8 zl = as_bf16x8(zt[(ks * 2 + 1) * 64 + lane]);
+        const bf16x8 z2 = as_bf16x8(zt[ks * 64 + lane]);
 #pragma unroll
-        for (int u = 0; u < TT; ++u) {
-          acc[u][NT] = mfma_bf16(zh, bq[u][ks], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[u][NT]);
-          acc[u][NT] = mfma_bf16(zl, bq[u][ks], acc[u][NT]);
-        }
+        for (int u = 0; u < TT; ++u)
+          acc[u][NT] = mfma_bf16(z2, bq[u][ks], ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[u][NT]);
       }
 #pragma unroll
       for (int u = 0; u < TT; ++u) {
-        // this tile's O_t(p) = num / den, weighted
-        const float r = ws[u] / acc[u][NT][0];
+        // this tile's O_t(p) = num / den (den: rows 4g and 4g + 1, the
+        // products with z's hi and lo parts), weighted; the hardware
+        // reciprocal (1 ulp) is far below the bf16 rounding of the output
+        const float r = ws[u] * __builtin_amdgcn_rcpf(acc[u][NT][0] + acc[u][NT][1]);
 #pragma unroll
         for (int i = 0; i < NT; ++i)
 #pragma unroll
@@ -398,13 +431,21 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
     }
 #pragma unroll
     for (int u = 0; u < TT; ++u) {
-      if (!tk[u].ok) continue;
-      const float rw = 1.0f / wacc[u];
+      if (!x.tk[u].ok) continue;
+      const float rw = __builtin_amdgcn_rcpf(wacc[u]);
       float out[Q4];
 #pragma unroll
       for (int c = 0; c < Q4; ++c) out[c] = oacc[u][c] * rw;
-      store_run<D, DT_BF16, DT_BF16>(oh + tk[u].off + gl * RN::CH * 2, out);
+      store_run<D, DT_BF16, DT_BF16>(oh + x.tk[u].off + gl * RN::CH * 2, out);
     }
+  };
+
+  for (int64_t base = base0; base < ntile; base += 2 * per_step) {
+    if (base + per_step < ntile) fetch(base + per_step, sb);
+    compute(sa);
+    if (base + per_step >= ntile) break;
+    if (base + 2 * per_step < ntile) fetch(base + 2 * per_step, sa);
+    compute(sb);
   }
 }
 
@@ -433,7 +474,11 @@ la_status make_tgeo(const la_tile_desc* td, int64_t heads, TGeo* g) {
   if (g->d != 16 && g->d != 32 && g->d != 64) return LA_ERR_UNSUPPORTED;
   for (int k = 0; k < 3; ++k)
     if (2 * g->halo[k] > g->core[k]) return LA_ERR_UNSUPPORTED;  // cells need <= 2 tiles per dim
-  if (heads > 65535 || tok > (int64_t(1) << 31) || cells > (int64_t(1) << 31)) return LA_ERR_UNSUPPORTED;
+  const int64_t field = td->dims[0] * td->dims[1] * td->dims[2];
+  // 32-bit token coordinates in the kernels; flat grids (cells >= tiles)
+  if (heads > 65535 || tok > 65536 || field >= (int64_t(1) << 31) ||
+      cells * heads >= (int64_t(1) << 31))
+    return LA_ERR_UNSUPPORTED;
   g->tile_tokens = tok;
   g->n_tiles = tiles;
   g->n_cells = cells;
@@ -472,15 +517,16 @@ hipError_t launch_tiled(const TGeo& g, const TLayout& L, const void* q, const vo
                         const void* v, void* o, char* ws, hipStream_t st) {
   {
     ProfScope prof("tile_summary", st);
-    hipLaunchKernelGGL(tile_summary_kernel<D>, dim3((unsigned)g.n_tiles, (unsigned)g.H),
-                       dim3(256), 0, st, g, k, v, (u32x4*)(ws + L.img));
+    hipLaunchKernelGGL(tile_summary_kernel<D>, dim3((unsigned)(g.n_tiles * g.H)), dim3(256), 0, st,
+                       g, k, v, (u32x4*)(ws + L.img));
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   {
     ProfScope prof("tile_apply", st);
-    hipLaunchKernelGGL(tile_apply_kernel<D>, dim3((unsigned)g.n_cells, (unsigned)g.H), dim3(512),
-                       0, st, g, q, o, (const void*)(ws + L.img));
+    hipLaunchKernelGGL(tile_apply_kernel<D>, dim3((unsigned)(g.n_cells * g.H)),
+                       dim3(64 * TiledCfg<D>::WAVES), 0, st,
+                       g, q, o, (const void*)(ws + L.img));
   }
   return hipGetLastError();
 }
