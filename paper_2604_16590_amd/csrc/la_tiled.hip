@@ -143,9 +143,11 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
       const uint32_t rem = j - ut * L12;
       uint32_t uy = rem / L2;
       uint32_t ux = rem - uy * L2;
+      // a whole step in range (all but a partial's last): no row checks
+      const bool full = (uint32_t)t0 + STEP <= tend;  // wave-uniform
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (j + r < tend) {
+        if (full || j + r < tend) {
           const uint32_t gt = clamp32(O0 + (int32_t)ut, M0);
           const uint32_t gy = clamp32(O1 + (int32_t)uy, M1);
           const uint32_t gx = clamp32(O2 + (int32_t)ux, M2);
@@ -160,9 +162,9 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
 #pragma unroll
           for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
         }
-        if (++ux == g.L[2]) {
+        if (++ux == L2) {
           ux = 0;
-          if (++uy == g.L[1]) {
+          if (++uy == L1) {
             uy = 0;
             ++ut;
           }
