@@ -494,7 +494,8 @@ def summarize_profiles(top, prof=None):
     lines = ["# rocprofv3 kernel statistics: long-context workload (B1 H8 N2097152 d128 bf16), "
              "fwd+bwd step",
              "# command: cd /tmp && TMPDIR=/tmp " + cmd % ("--kernel-trace --stats",
-                                                          "/root/repo/gpurun_out/prof/trace"),
+                                                          "DIR/trace"),
+             "# (DIR: the rocprofv3 output directory later given to bench.py --summarize-profiles)",
              "# 2 warm-up + 5 timed steps, then 1 warm-up and 5 forward-only steps inside bench.py;",
              "# kernel = the name bench.py reports (its HIP-event averages cover the same launches)",
              "# bench_avg_ns: the same kernel's average over the timed steps by the bench's own "
@@ -547,13 +548,14 @@ def summarize_profiles(top, prof=None):
              "# long-context workload, bf16 fwd+bwd; each counter scaled by what it reads for the "
              "library's plain 1 GiB device copy",
              "# commands: cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc FETCH_SIZE",
-                                                            "/root/repo/gpurun_out/prof/fetch"),
+                                                            "DIR/fetch"),
              "#           cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc WRITE_SIZE",
-                                                            "/root/repo/gpurun_out/prof/write"),
+                                                            "DIR/write"),
              "#           cd /tmp && TMPDIR=/tmp " + cal % ("--pmc FETCH_SIZE",
-                                                            "/root/repo/gpurun_out/prof/copy_fetch"),
+                                                            "DIR/copy_fetch"),
              "#           cd /tmp && TMPDIR=/tmp " + cal % ("--pmc WRITE_SIZE",
-                                                            "/root/repo/gpurun_out/prof/copy_write"),
+                                                            "DIR/copy_write"),
+             "# (DIR: the rocprofv3 output directory later given to bench.py --summarize-profiles)",
              "# copy of 1 GiB: FETCH_SIZE %.0f KiB (factor %.4f), WRITE_SIZE %.0f KiB (factor %.4f)"
              % (copy_f[0][0], f_fac, copy_w[0][0], w_fac),
              "%-14s %12s %12s %14s %14s" % ("kernel", "fetch_KiB", "write_KiB", "hbm_GB/launch",
@@ -588,7 +590,8 @@ def summarize_mfma(directory, prof, cmd, avg_ms):
     lines = ["# matrix-core work per launch from rocprofv3 counters: long-context workload, bf16 "
              "fwd+bwd",
              "# command: cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc " + MFMA_COUNTERS,
-                                                          "/root/repo/gpurun_out/prof/mfma"),
+                                                          "DIR/mfma"),
+             "# (DIR: the rocprofv3 output directory later given to bench.py --summarize-profiles)",
              "# SQ_INSTS_VALU_MFMA_MOPS_BF16 counts bf16 matrix-core work in units of 512 FLOPs "
              "(summed over the chip);",
              "# TFLOP/s uses the kernel's average duration from kernel_stats_long_context_bf16.txt; "
