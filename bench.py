@@ -498,10 +498,22 @@ def summarize_profiles(top, prof=None):
              "# (DIR: the rocprofv3 output directory later given to bench.py --summarize-profiles)",
              "# 2 warm-up + 5 timed steps, then 1 warm-up and 5 forward-only steps inside bench.py;",
              "# kernel = the name bench.py reports (its HIP-event averages cover the same launches)",
-             "# bench_avg_ns: the same kernel's average over the timed steps by the bench's own "
-             "HIP events in this run",
-             "%-14s %-60s %6s %14s %12s %7s %13s" % ("kernel", "name", "calls", "total_ns", "avg_ns",
-                                                    "pct", "bench_avg_ns")]
+             "# median_ns: the median launch in the kernel trace (the first, cold launches count "
+             "in avg_ns); bench_avg_ns: the same kernel's average over the timed steps by the "
+             "bench's own HIP events in this run",
+             "%-14s %-60s %6s %14s %12s %7s %12s %13s" % ("kernel", "name", "calls", "total_ns",
+                                                         "avg_ns", "pct", "median_ns",
+                                                         "bench_avg_ns")]
+    durs = {}
+    trace_csv = [os.path.join(b, f) for b, _, fs in os.walk(os.path.join(top, "trace"))
+                 for f in fs if f.endswith("kernel_trace.csv")]
+    if len(trace_csv) == 1:
+        for r in read_csv(trace_csv[0]):
+            durs.setdefault(r["Kernel_Name"], []).append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    def median(v):
+        v = sorted(v)
+        return v[len(v) // 2] if v else None
     events = {}
     trace_out = os.path.join(top, "trace.out")
     if os.path.isfile(trace_out):
@@ -509,9 +521,11 @@ def summarize_profiles(top, prof=None):
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         pname = profile_name(r["Name"])
         ev = events.get(pname if pname != "combine_bwd" else "", None)
-        lines.append("%-14s %-60s %6s %14s %12.0f %7.2f %13s" % (
+        med = median(durs.get(r["Name"], []))
+        lines.append("%-14s %-60s %6s %14s %12.0f %7.2f %12s %13s" % (
             pname or "-", r["Name"][:60], r["Calls"], r["TotalDurationNs"],
-            float(r["AverageNs"]), float(r["Percentage"]), "%.0f" % ev if ev else "-"))
+            float(r["AverageNs"]), float(r["Percentage"]), "%d" % med if med else "-",
+            "%.0f" % ev if ev else "-"))
     with open(os.path.join(prof, "kernel_stats_long_context_bf16.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     # HBM traffic
