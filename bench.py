@@ -553,7 +553,21 @@ def summarize_profiles(top, prof=None):
                        "hbm_bytes_per_launch": (fk * f_fac + wk * w_fac) * 1024.0,
                        "alg_bytes_per_launch": KERNEL_PASSES.get(base, 0) * elems * 2,
                        "dispatches": fetch.get(name, (0.0, 0))[1]}
-    rec = {"source_digest": source_digest(), "copy_factor_fetch": f_fac, "copy_factor_write": w_fac,
+    # the digest of the sources the counted runs used (their bench lines
+    # carry it), so that counters taken on other sources never pass for
+    # the current ones
+    run_digests = set()
+    for name in ("trace.out", "fetch.out", "write.out"):
+        path = os.path.join(top, name)
+        if os.path.isfile(path):
+            run_digests.add(last_json_line(path).get("source_digest"))
+    if len(run_digests) != 1 or None in run_digests:
+        raise SystemExit("the profiled runs carry no common source digest: %s" % sorted(map(str, run_digests)))
+    run_digest = run_digests.pop()
+    if run_digest != source_digest():
+        print("note: the profiled runs used other kernel sources than these; the bench will "
+              "report traffic null until the counters are taken again", file=sys.stderr)
+    rec = {"source_digest": run_digest, "copy_factor_fetch": f_fac, "copy_factor_write": w_fac,
            "kernels": kern}
     with open(os.path.join(prof, "counters_long_context_bf16.json"), "w") as f:
         json.dump(rec, f, indent=1)
@@ -855,6 +869,8 @@ def main():
         "cpu_baseline": cpu,
         "errors_vs_oracle_on_sample": errors,
         "cpu_baseline_other_workloads": cpu_others,
+        # the step's kernel sources this line was measured with
+        "source_digest": source_digest(),
     }
     print(json.dumps(result), flush=True)
 

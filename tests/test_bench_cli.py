@@ -86,6 +86,9 @@ def test_profile_summaries_from_rocprof_csv(tmp_path):
                _counter_rows("FETCH_SIZE", [(COPY, [524288.0, 524288.0])]))
     _write_csv(str(top / "copy_write" / "run_counter_collection.csv"), COUNTER_HEADER,
                _counter_rows("WRITE_SIZE", [(COPY, [1048576.0])]))
+    # the profiled runs' bench lines carry the digest of their sources
+    for name in ("trace.out", "fetch.out", "write.out"):
+        (top / name).write_text("log line\n" + json.dumps({"kernels": {}, "source_digest": bench.source_digest()}) + "\n")
     out = tmp_path / "profiles"
     out.mkdir()
     bench.summarize_profiles(str(top), str(out))
@@ -98,3 +101,8 @@ def test_profile_summaries_from_rocprof_csv(tmp_path):
     assert k["alg_bytes_per_launch"] == 4 * 8 * 2097152 * 128 * 2
     stats = open(out / "kernel_stats_long_context_bf16.txt").read()
     assert "bwd_key" in stats and "3000000" in stats
+    # runs on other sources are refused a current digest
+    (top / "write.out").write_text(json.dumps({"kernels": {}, "source_digest": "other"}) + "\n")
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.summarize_profiles(str(top), str(out))
