@@ -134,3 +134,59 @@ def test_fused_tiled_forward_bitwise_deterministic_and_full_grid_shape():
     err = normwise(as64(a).reshape(1, 1, -1), ref.reshape(1, 1, -1))
     print("fused tiled 16x32x64 normwise", err, flush=True)
     assert err < TOL["bf16"]
+
+
+def test_fused_tiled_forward_full_size_sampled_positions():
+    # the bench's geometry: a T256 x 64 x 128 grid, 16 heads of d = 64,
+    # cores 8 x 16 x 16, halos 2 x 4 x 4 (1,024 tiles of 6,912 tokens).
+    # Sampled positions (corners, borders, halo overlaps, random) of two
+    # heads against the oracle, one position at a time: every covering
+    # tile's extended, border-clamped token set gathered from the field,
+    # the oracle's summary of it applied to the position's query, and the
+    # oracle's Hann weights
+    dev = require_gpu()
+    dims, core, halo, H, d = (256, 64, 128), (8, 16, 16), (2, 4, 4), 16, 64
+    fields = []
+    for sid in range(3):
+        x = torch.empty(dims + (H, d), dtype=torch.bfloat16, device=dev)
+        la.gen_fill(x.view(1, 1, -1, H * d), seed=1004, stream_id=sid)
+        fields.append(x)
+    out = la.tiled_forward(*fields, core, halo)
+    torch.cuda.synchronize()
+    _, L = la.tile_geometry(dims, core, halo)
+    n = [(dims[k] + core[k] - 1) // core[k] for k in range(3)]  # tiles per dimension
+    rng = np.random.default_rng(9)
+    positions = [(0, 0, 0), (255, 63, 127), (0, 63, 0), (255, 0, 127), (7, 15, 15), (8, 16, 16),
+                 (9, 17, 18), (6, 12, 12), (128, 32, 64)]
+    positions += [tuple(int(rng.integers(0, m)) for m in dims) for _ in range(5)]
+    got, want = [], []
+    for p in positions:
+        cover = []
+        for k in range(3):
+            cover.append([j for j in range(n[k])
+                          if j * core[k] - halo[k] <= p[k] < (j + 1) * core[k] + halo[k]])
+        for h in (0, 15):
+            acc, wsum = np.zeros(d), 0.0
+            q = to_host(fields[0][p[0], p[1], p[2], h].reshape(1, 1, 1, d))
+            for jt in cover[0]:
+                for jy in cover[1]:
+                    for jx in cover[2]:
+                        js = (jt, jy, jx)
+                        w = 1.0
+                        for k in range(3):
+                            w *= oracle.hann(p[k] - (js[k] * core[k] - halo[k]), L[k])
+                        if w == 0.0:
+                            continue
+                        idx = [torch.clamp(torch.arange(L[k], device=dev) + js[k] * core[k] - halo[k],
+                                           0, dims[k] - 1) for k in range(3)]
+                        gt, gy, gx = torch.meshgrid(*idx, indexing="ij")
+                        kt, vt = (to_host(f[gt, gy, gx, h].reshape(1, 1, -1, d)) for f in fields[1:])
+                        S_t, z_t = oracle.summary(as64(kt), as64(vt))
+                        acc += w * oracle.apply(as64(q), S_t, z_t)[0, 0, 0]
+                        wsum += w
+            want.append(acc / wsum)
+            got.append(as64(out[p[0], p[1], p[2], h].reshape(d)))
+    err = np.linalg.norm(np.array(got) - np.array(want)) / np.linalg.norm(np.array(want))
+    print("fused tiled full size, %d sampled (position, head) outputs: normwise %.3g"
+          % (len(got), err), flush=True)
+    assert err < TOL["bf16"]
