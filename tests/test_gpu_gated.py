@@ -135,3 +135,32 @@ def test_strided_bnhd_gated_matches_contiguous():
     dense = la.forward_gated(*(to_device(x, dev) for x in (q, k, v, other)), sig, 0.5)
     torch.cuda.synchronize()
     assert torch.equal(out.contiguous(), dense)
+
+
+def test_long_context_cached_apply_and_gated_in_place_sampled_rows():
+    # the bench's summary-reuse and gated shapes: B1 H8, 2,097,152 tokens,
+    # d = 128, bf16 N(0, 0.5).  New queries against the forward's kept
+    # (S, z), then the gated apply blended in place into the other branch;
+    # ~2,000 sampled rows of every head (the last row included) against the
+    # oracle's apply of the same (S, z) and its gated mix
+    from gpu_util import to_host
+    dev = require_gpu()
+    B, H, N, d = 1, 8, 2097152, 128
+    xs = [torch.empty((B, H, N, d), dtype=torch.bfloat16, device=dev) for _ in range(5)]
+    for sid, x in enumerate(xs):  # q, k, v, the step's new queries, the other branch
+        la.gen_fill(x, seed=77, stream_id=sid, std=0.5 ** 0.5)
+    _, S, z = la.forward(*xs[:3], return_summary=True)
+    o2 = la.apply(xs[3], S, z)
+    rows = sorted(set(np.random.default_rng(5).integers(0, N, 2048).tolist()) | {0, N - 1})
+    idx = torch.tensor(rows, device=dev)
+    other0 = to_host(xs[4][:, :, idx])
+    sigma = torch.tensor([0.7], dtype=torch.float64, device=dev)
+    gated = la.apply_gated(xs[3], S, z, xs[4], sigma, 0.5, out=xs[4])
+    torch.cuda.synchronize()
+    ref = oracle.apply(to_host(xs[3][:, :, idx]), S.cpu().numpy(), z.cpu().numpy())
+    err = normwise(as64(o2[:, :, idx]), ref)
+    ref_g = oracle.gated_mix(ref, other0, [0.7], 0.5)
+    err_g = normwise(as64(gated[:, :, idx]), ref_g)
+    print("long context: cached apply %.3g, gated in place %.3g" % (err, err_g), flush=True)
+    assert err < TOL["bf16"] and err_g < TOL["bf16"]
+    assert gated.data_ptr() == xs[4].data_ptr()
