@@ -262,16 +262,24 @@ la_status la_tile_blend(const la_tile_desc* desc, const void* tiles, void* field
  * w_t the tile's Hann weight at p -- except that the tile outputs O_t are
  * kept in FP32 instead of being rounded to bf16, and S_t enters as its bf16
  * hi part (about 2^-9 relative; z_t as hi + lo).  Pass 1 reads K and V in
- * place and keeps per (tile, head) only S_t, z_t as matrix-core operands;
- * pass 2 reads Q once and writes O once.  Requirements beyond
- * la_tile_desc's: dtype LA_BF16, d = C / heads in {16, 32, 64},
- * 2 * halo <= core in every dimension (then each position lies in at most
- * two tiles per dimension), at most 65,536 tokens per extended tile and
- * fewer than 2^31 tokens per field; otherwise LA_ERR_UNSUPPORTED.  The
+ * place, walking each (y, x) segment pair of the tiles' extended ranges
+ * along t so that a token shared by neighbouring tiles is mapped once per
+ * segment pair; it sums in FP32 runs of at most 16,384 tokens, adds a
+ * tile's runs in FP64 in a fixed order (results are bitwise reproducible)
+ * and keeps per (tile, head) only S_t, z_t as matrix-core operands; pass 2
+ * reads Q once and writes O once.  Requirements beyond la_tile_desc's:
+ * dtype LA_BF16, d = C / heads in {16, 32, 64}, 2 * halo <= core in every
+ * dimension (then each position lies in at most two tiles per dimension),
+ * at most 65,536 tokens per extended tile and 16,384 along t (core[0] +
+ * 2 * halo[0]), fewer than 2^31 tokens per field; otherwise
+ * LA_ERR_UNSUPPORTED.  The
  * Hann weights use the hardware sine and the divisions by den and by the
  * weight sum the hardware reciprocal (about 1e-6 relative, far below the
  * bf16 rounding of o).
- * ws: ws_bytes >= la_tiled_workspace_size(desc, heads), 256-byte aligned.
+ * ws: ws_bytes >= la_tiled_workspace_size(desc, heads), 256-byte aligned
+ * (per head: one operand slot per tile, and n_t (2 n_y + 1)(2 n_x + 1)
+ * FP32 column sums of d^2 + d floats, times the footprint parts when a
+ * segment pair's run would exceed 16,384 tokens; n_* tiles per dimension).
  */
 la_status la_tiled_workspace_size(const la_tile_desc* desc, int64_t heads, size_t* bytes);
 la_status la_tiled_forward(const la_tile_desc* desc, int64_t heads, const void* q, const void* k,

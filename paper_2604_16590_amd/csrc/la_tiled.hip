@@ -11,12 +11,15 @@
 //     O_t(p) = phi(q_p)^T S_t / (phi(q_p) . z_t),
 // over the tiles t covering grid position p.  Nothing per tile is stored
 // but (S_t, z_t):
-//  1. tile summaries: each tile's extended token set is read from the K
-//     and V fields in place (clamped coordinates, as tile extraction does)
-//     by one workgroup per (tile, head), summed by the summary machinery
-//     (four FP32 partials of at most 16,384 tokens), the partials added in
-//     FP64 in a fixed order, and the result written as the apply's operands
-//     (S_t^T hi parts, z_t hi + lo);
+//  1. tile summaries, read from the K and V fields in place (clamped
+//     coordinates, as tile extraction does).  Neighbouring tiles share
+//     their halo tokens, so the extended token sets are cut into segment
+//     pairs in (y, x) and walked along t: each token's phi(k) and operands
+//     are formed once per segment pair and added into the FP32 sums of the
+//     one or two t-neighbouring tiles that hold it (1a, column partials of
+//     at most 16,384 tokens); each tile's column partials are then added
+//     in FP64 in a fixed order and written as the apply's operands (1b:
+//     S_t^T hi parts, z_t hi + lo);
 //  2. apply and blend: the grid is cut into cells between tile centres,
 //     whose positions are covered by at most two tiles per dimension (when
 //     every halo is at most half its core), so a workgroup stages the
@@ -43,17 +46,19 @@ struct TGeo {
   int64_t C;         // channels: heads * d
   int64_t H, d;
   int64_t tile_tokens, n_tiles, n_cells;
-  int P, Tw;         // partials per (tile, head), tokens per partial
+  int64_t ns[3];     // segments per dimension (y, x): 2n + 1
+  int Pf;            // parts per segment pair footprint (<= 8)
+  int64_t CH, nch;   // tiles per t chunk, chunks
+  int64_t n_items;   // column walks: nch * ns[1] * ns[2] * Pf * H
 };
 
 __device__ __forceinline__ uint32_t clamp32(int32_t v, int32_t hi) {
   return (uint32_t)min(max(v, 0), hi);
 }
 
-// Hann weight of coordinate u of a tile extent L (cell centres, strictly
-// positive on [0, L)): sin^2(pi (u + 1/2) / L); zero outside the tile.
-// w(u) = sin^2(pi (u + 1/2) / L) for 0 <= u < L, else 0; inv2L = 1 / (2L).
-// The hardware sine takes its argument in revolutions (sin(2 pi x)); its
+// Hann weight of coordinate u of a tile extent L, sampled at cell centres:
+// w(u) = sin^2(pi (u + 1/2) / L) for 0 <= u < L (strictly positive), else
+// 0; inv2L = 1 / (2L).  The hardware sine takes its argument in revolutions (sin(2 pi x)); its
 // error (about 1e-6) is far below the bf16 rounding of the blended output.
 __device__ __forceinline__ float hann_w(int32_t u, int32_t L, float inv2L) {
   const float s = __builtin_amdgcn_sinf(((float)u + 0.5f) * inv2L);
@@ -81,151 +86,325 @@ struct TiledCfg {
 };
 
 // ---------------------------------------------------------------------------
-// Pass 1: per (tile, head), the summary over the tile's extended token set
-// [ut][uy][ux] (row-major), coordinates clamped into the grid.  One
-// workgroup per (tile, head); wave w sums tokens [w*Tw, w*Tw + Tw) in FP32
-// (Tw <= 16,384), the four partials are added in FP64 in a fixed order
-// through LDS, and the result is written as the apply's operand slot.
-// grid: one workgroup per (tile, head), head fastest: the H workgroups of
-// a tile run side by side and together read whole token rows (each reads
-// only its head's d features of a row).
+// Pass 1: the tile summaries, with phi(k) and the operand packing done once
+// per token and t-neighbourhood instead of once per covering tile.  Along
+// y and x, tile j's extended range [jc - h, (j+1)c + h) is the union of
+// three segments: Z_j = [jc - h, jc + h) (shared with tile j - 1), I_j =
+// [jc + h, (j+1)c - h) (its own) and Z_{j+1}; numbered s = 2j (Z_j) and
+// s = 2j + 1 (I_j), tile j covers segments 2j, 2j + 1 and 2j + 2.
+//  1a. One wave per (t chunk, y segment, x segment, footprint part, head)
+//      walks the t planes of its chunk's tiles over that segment pair,
+//      coordinates clamped into the grid.  A plane lies in at most two
+//      tiles of the chunk (2 halo <= core): the wave keeps both tiles' FP32
+//      sums and adds each step's products into the one or two that hold
+//      the plane, from the same rounded operands.  After a tile's last
+//      plane its sum is written out as the tile's column partial for this
+//      segment pair (an FP32 run of at most 16,384 tokens).
+//  1b. One workgroup per (tile, head) adds its column partials (3 x 3
+//      segment pairs times the footprint parts) in FP64 in a fixed order
+//      and writes the apply's operand slot.
 // ---------------------------------------------------------------------------
+
+// segment s of dimension k (1 or 2): first virtual coordinate and width
+__device__ __forceinline__ void segment(const TGeo& g, int k, int64_t s, int32_t& start,
+                                        int32_t& width) {
+  const int32_t j = (int32_t)(s >> 1), c = (int32_t)g.core[k], h = (int32_t)g.halo[k];
+  start = (s & 1) ? j * c + h : j * c - h;
+  width = (s & 1) ? c - 2 * h : 2 * h;
+}
+
+// part f of the (y, x) footprint of segment pair (sy, sx): positions
+// [p0, p1) of the footprint, row-major; false when it is empty (a
+// zero-width segment, or fewer positions than parts)
+__device__ __forceinline__ bool col_part(const TGeo& g, int64_t sy, int64_t sx, int f, int32_t& ys,
+                                         int32_t& xs, uint32_t& xw, uint32_t& p0, uint32_t& p1) {
+  int32_t yw, w;
+  segment(g, 1, sy, ys, yw);
+  segment(g, 2, sx, xs, w);
+  xw = (uint32_t)w;
+  const uint32_t fp = (uint32_t)yw * xw;
+  const uint32_t pl = (fp + (uint32_t)g.Pf - 1) / (uint32_t)g.Pf;
+  p0 = (uint32_t)f * pl;
+  p1 = min(fp, p0 + pl);
+  return p0 < p1;
+}
+
+// the column partial of tile row a (along t), segment pair (sy, sx), part
+// f, head: D*D + D floats (S in the matrix cores' lane order, then z)
+__device__ __forceinline__ int64_t col_index(const TGeo& g, int64_t a, int64_t sy, int64_t sx, int f,
+                                             int64_t head) {
+  return (((a * g.ns[1] + sy) * g.ns[2] + sx) * g.Pf + f) * g.H + head;
+}
+
+// One step of a column walk (R tokens per lane group, loaded as the
+// summary step takes them): phi on the keys and the token-pair packing
+// once, then the products into the current tile's sum and, on a plane
+// shared with the next tile, into that one's too.
 template <int D>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restrict__ v,
-                         u32x4* __restrict__ slots) {
+__device__ __forceinline__ void col_step(const SummaryRegs<DT_BF16, D, MODE_FWD>& x, bool both,
+                                         f32x4 (&ac)[D / 16][D / 16], float (&zc)[D / 16],
+                                         f32x4 (&an)[D / 16][D / 16], float (&zn)[D / 16]) {
+  constexpr int F = D / 16;
+  uint32_t own[F][4];
+#pragma unroll
+  for (int jj = 0; jj < F; ++jj)
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp)
+      own[jj][pp] = (uint32_t)word_bits16<DT_BF16>(x.vw[2 * pp], jj) |
+                    ((uint32_t)word_bits16<DT_BF16>(x.vw[2 * pp + 1], jj) << 16);
+  bf16x8 ak[F];
+#pragma unroll
+  for (int i = 0; i < F; ++i) {
+    uint32_t pk[4];
+    float zs = 0.f;
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      pk[pp] = pack_bf16(phi<DT_BF16>(word_elem<DT_BF16>(x.kw[2 * pp], i)),
+                         phi<DT_BF16>(word_elem<DT_BF16>(x.kw[2 * pp + 1], i)));
+      // normaliser from the same rounded phi values that feed S
+      zs = add_bf16_pair(zs, pk[pp]);
+    }
+    zc[i] += zs;
+    if (both) zn[i] += zs;
+    ak[i] = as_bf16x8(u32x4{pk[0], pk[1], pk[2], pk[3]});
+  }
+#pragma unroll
+  for (int j = 0; j < F; ++j) {
+    const bf16x8 bv = as_bf16x8(u32x4{own[j][0], own[j][1], own[j][2], own[j][3]});
+#pragma unroll
+    for (int i = 0; i < F; ++i) ac[i][j] = mfma_bf16(ak[i], bv, ac[i][j]);
+  }
+  if (both) {
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      const bf16x8 bv = as_bf16x8(u32x4{own[j][0], own[j][1], own[j][2], own[j][3]});
+#pragma unroll
+      for (int i = 0; i < F; ++i) an[i][j] = mfma_bf16(ak[i], bv, an[i][j]);
+    }
+  }
+}
+
+// 1a. grid: four waves per workgroup, each its own item; items ordered
+// head fastest, so the waves reading one token row's head slices run side
+// by side.  One wave per SIMD: at d = 64 the two tiles' sums, the two
+// register sets of tokens and the operands take about 256 registers (two
+// waves per SIMD spilled and ran 5 % slower)
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+void tile_cols_kernel(TGeo g, const void* __restrict__ k, const void* __restrict__ v,
+                      float* __restrict__ cols) {
   using C = SummaryCfg<DT_BF16, D, MODE_FWD>;
-  using TC = TiledCfg<D>;
-  using RB = Run<D, DT_BF16>;
-  static_assert(C::SPLIT == 1, "one wave per partial");
-  constexpr int F = C::F, FR = C::FR, R = C::R, STEP = C::STEP;
-  constexpr int E = D * D + D;
-  __shared__ __align__(16) float red[4][E];
-  const int lane = threadIdx.x & 63, wave = wave_index();
+  using Regs = SummaryRegs<DT_BF16, D, MODE_FWD>;
+  static_assert(C::SPLIT == 1 && C::FR == C::F, "one wave holds a whole sum");
+  constexpr int F = C::F, R = C::R, STEP = C::STEP, E = D * D + D;
+  const int lane = threadIdx.x & 63;
   const int gq = lane >> 4, m = lane & 15;
-  const int64_t tile = blockIdx.x / g.H;
-  const int p = wave;
-  const int64_t head = blockIdx.x % g.H;
-  const int64_t t_begin = (int64_t)p * g.Tw;
-  const int64_t t_end = min(g.tile_tokens, t_begin + (int64_t)g.Tw);
-  float* out = red[p];
-  // the tile's origin in the grid (core start minus halo)
-  const int64_t a = tile / (g.n[1] * g.n[2]), b = (tile / g.n[2]) % g.n[1], c = tile % g.n[2];
-  const int64_t o0 = a * g.core[0] - g.halo[0], o1 = b * g.core[1] - g.halo[1],
-                o2 = c * g.core[2] - g.halo[2];
+  const int64_t item = (int64_t)blockIdx.x * 4 + wave_index();
+  if (item >= g.n_items) return;  // uniform over the wave
+  const int64_t head = item % g.H;
+  int64_t rest = item / g.H;
+  const int f = (int)(rest % g.Pf);
+  rest /= g.Pf;
+  const int64_t sx = rest % g.ns[2];
+  rest /= g.ns[2];
+  const int64_t sy = rest % g.ns[1];
+  const int64_t q = rest / g.ns[1];
+  int32_t ys, xs;
+  uint32_t xw, p0, p1;
+  if (!col_part(g, sy, sx, f, ys, xs, xw, p0, p1)) return;  // uniform
+  const int64_t a0 = q * g.CH, a1 = min(g.n[0], a0 + g.CH);
+  const int32_t c0 = (int32_t)g.core[0], h0 = (int32_t)g.halo[0];
+  // virtual planes [t_first, t_stop): the chunk's tiles' extended t ranges
+  const int32_t t_first = (int32_t)a0 * c0 - h0, t_stop = (int32_t)a1 * c0 + h0;
+  const uint32_t spp = (p1 - p0 + STEP - 1) / STEP;  // steps per plane
+  const int64_t total = (int64_t)(t_stop - t_first) * spp;
+
   const int64_t rowb = g.C * 2;  // bytes per token of a field
   const char* kb = (const char*)k + head * D * 2 + (int64_t)(F * m) * 2;
   const char* vb = (const char*)v + head * D * 2 + (int64_t)(F * m) * 2;
-  f32x4 acc[FR][F];
-  float zacc[FR];
+  const int32_t M0 = (int32_t)g.dims[0] - 1, M1 = (int32_t)g.dims[1] - 1,
+                M2 = (int32_t)g.dims[2] - 1;
+  const uint32_t N1 = (uint32_t)g.dims[1], N2 = (uint32_t)g.dims[2];
+  const uint32_t neg_inf = 0xff80ff80u;
+  // the step js of plane t: lane group gq takes footprint positions
+  // p0 + STEP*js + R*gq + r; 32-bit coordinates (a field holds fewer
+  // than 2^31 tokens)
+  auto load = [&](int32_t t, uint32_t js, Regs& x) {
+    const uint32_t j = p0 + STEP * js + R * gq;
+    uint32_t uy = j / xw;
+    uint32_t ux = j - uy * xw;
+    const uint32_t gt = clamp32(t, M0);
+    const bool full = p0 + STEP * (js + 1) <= p1;  // wave-uniform
 #pragma unroll
-  for (int i = 0; i < FR; ++i) {
-    zacc[i] = 0.f;
+    for (int r = 0; r < R; ++r) {
+      if (full || j + r < p1) {
+        const uint32_t gy = clamp32(ys + (int32_t)uy, M1);
+        const uint32_t gx = clamp32(xs + (int32_t)ux, M2);
+        const int64_t off = (int64_t)((gt * N1 + gy) * N2 + gx) * rowb;
+        load_words<C::KB>(kb + off, x.kw[r]);
+        load_words<C::VB>(vb + off, x.vw[r]);
+      } else {
 #pragma unroll
-    for (int j = 0; j < F; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-  if (t_begin < t_end) {
-    const uint32_t neg_inf = 0xff80ff80u;
-    uint32_t* xch = nullptr;
-    // the step at t0: lane group gq takes tokens t0 + R*gq + r; decompose
-    // the first one, then walk in (ut, uy, ux) order.  32-bit throughout
-    // (an extended tile holds at most 65,536 tokens, the field fewer than
-    // 2^31), so the walk costs a few instructions per token
-    const uint32_t L1 = (uint32_t)g.L[1], L2 = (uint32_t)g.L[2], L12 = L1 * L2;
-    const int32_t O0 = (int32_t)o0, O1 = (int32_t)o1, O2 = (int32_t)o2;
-    const int32_t M0 = (int32_t)g.dims[0] - 1, M1 = (int32_t)g.dims[1] - 1,
-                  M2 = (int32_t)g.dims[2] - 1;
-    const uint32_t N1 = (uint32_t)g.dims[1], N2 = (uint32_t)g.dims[2];
-    const uint32_t tend = (uint32_t)t_end;
-    auto load = [&](int64_t t0, SummaryRegs<DT_BF16, D, MODE_FWD>& x) {
-      const uint32_t j = (uint32_t)t0 + R * gq;
-      uint32_t ut = j / L12;
-      const uint32_t rem = j - ut * L12;
-      uint32_t uy = rem / L2;
-      uint32_t ux = rem - uy * L2;
-      // a whole step in range (all but a partial's last): no row checks
-      const bool full = (uint32_t)t0 + STEP <= tend;  // wave-uniform
+        for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (full || j + r < tend) {
-          const uint32_t gt = clamp32(O0 + (int32_t)ut, M0);
-          const uint32_t gy = clamp32(O1 + (int32_t)uy, M1);
-          const uint32_t gx = clamp32(O2 + (int32_t)ux, M2);
-          const int64_t off = (int64_t)((gt * N1 + gy) * N2 + gx) * rowb;
-          // plain loads: halo tokens are read again by the neighbouring
-          // tiles, dispatched at about the same time
-          load_words<C::KB>(kb + off, x.kw[r]);
-          load_words<C::VB>(vb + off, x.vw[r]);
-        } else {
-#pragma unroll
-          for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
-#pragma unroll
-          for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
-        }
-        if (++ux == L2) {
-          ux = 0;
-          if (++uy == L1) {
-            uy = 0;
-            ++ut;
-          }
-        }
+        for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
       }
-    };
-    // two register sets in turn: the next step's loads are in flight while
-    // the current one computes
-    SummaryRegs<DT_BF16, D, MODE_FWD> ra, rb;
-    int64_t t0 = t_begin;
-    load(t0, ra);
-    while (true) {
-      const int64_t t1 = t0 + STEP;
-      if (t1 < t_end) load(t1, rb);
-      summary_step<DT_BF16, D, MODE_FWD>(ra, 0, lane, xch, acc, zacc);
-      if (t1 >= t_end) break;
-      const int64_t t2 = t1 + STEP;
-      if (t2 < t_end) load(t2, ra);
-      summary_step<DT_BF16, D, MODE_FWD>(rb, 0, lane, xch, acc, zacc);
-      if (t2 >= t_end) break;
-      t0 = t2;
+      if (++ux == xw) {
+        ux = 0;
+        ++uy;
+      }
+    }
+  };
+
+  f32x4 ac[F][F], an[F][F];
+  float zc[F], zn[F];
+#pragma unroll
+  for (int i = 0; i < F; ++i) {
+    zc[i] = 0.f;
+    zn[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+      ac[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      an[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
   }
+  int64_t a = a0;  // the tile whose sum is ac; an is tile a + 1's
+  auto process = [&](const Regs& x, int32_t t, uint32_t js) {
+    const int32_t next_first = (int32_t)(a + 1) * c0 - h0;  // tile a + 1's first plane
+    col_step<D>(x, a + 1 < a1 && t >= next_first, ac, zc, an, zn);
+    if (js == spp - 1 && t == next_first + 2 * h0 - 1) {  // tile a's last plane done
+      float* out = cols + col_index(g, a, sy, sx, f, head) * E;
 #pragma unroll
-  for (int i = 0; i < FR; ++i)
+      for (int i = 0; i < F; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j) *(f32x4*)(out + ((i * F + j) * 64 + lane) * 4) = acc[i][j];
+        for (int j = 0; j < F; ++j) *(f32x4*)(out + ((i * F + j) * 64 + lane) * 4) = ac[i][j];
 #pragma unroll
-  for (int i = 0; i < FR; ++i) {
-    const float zs = sum_groups(zacc[i]);
-    if (gq == 0) out[D * D + F * m + i] = zs;
+      for (int i = 0; i < F; ++i) {
+        const float zs = sum_groups(zc[i]);
+        if (gq == 0) out[D * D + F * m + i] = zs;
+      }
+#pragma unroll
+      for (int i = 0; i < F; ++i) {
+        zc[i] = zn[i];
+        zn[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+          ac[i][j] = an[i][j];
+          an[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      ++a;
+    }
+  };
+  auto advance = [&](int32_t& t, uint32_t& js) {
+    if (++js == spp) {
+      js = 0;
+      ++t;
+    }
+  };
+  // two register sets in turn, the next step's loads in flight while the
+  // current one computes; every load is issued (past the last step the
+  // last one is read again, unused), so a step waits only for its own
+  int32_t lt = t_first, ct = t_first;
+  uint32_t ljs = 0, cjs = 0;
+  auto advance_load = [&]() {
+    if (lt != t_stop - 1 || ljs != spp - 1) advance(lt, ljs);
+  };
+  Regs ra, rb;
+  load(lt, ljs, ra);
+  advance_load();
+  for (int64_t s = 0; s < total; s += 2) {
+    load(lt, ljs, rb);
+    advance_load();
+    process(ra, ct, cjs);
+    advance(ct, cjs);
+    load(lt, ljs, ra);
+    advance_load();
+    if (s + 1 < total) {
+      process(rb, ct, cjs);
+      advance(ct, cjs);
+    }
+  }
+}
+
+// 1b. grid: one workgroup per (tile, head), head fastest
+template <int D>
+__global__ __launch_bounds__(256)
+void tile_slot_kernel(TGeo g, const float* __restrict__ cols, u32x4* __restrict__ slots) {
+  using TC = TiledCfg<D>;
+  using RB = Run<D, DT_BF16>;
+  constexpr int F = D / 16, E = D * D + D;
+  static_assert(E % 4 == 0, "whole 16-byte groups of a partial");
+  const int64_t tile = blockIdx.x / g.H;
+  const int64_t head = blockIdx.x % g.H;
+  const int64_t a = tile / (g.n[1] * g.n[2]), b = (tile / g.n[2]) % g.n[1], c = tile % g.n[2];
+  // the tile's column partials (at most 9 x 8), in a fixed order
+  __shared__ int64_t src[9 * 8];
+  __shared__ int nsrc;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int64_t sy = 2 * b; sy <= 2 * b + 2; ++sy)
+      for (int64_t sx = 2 * c; sx <= 2 * c + 2; ++sx)
+        for (int f = 0; f < g.Pf; ++f) {
+          int32_t ys, xs;
+          uint32_t xw, p0, p1;
+          if (col_part(g, sy, sx, f, ys, xs, xw, p0, p1)) src[n++] = col_index(g, a, sy, sx, f, head) * E;
+        }
+    nsrc = n;
   }
   __syncthreads();
-  // FP64 sum of the four partials, (p0 + p1) + (p2 + p3), element u of the
-  // partial layout (tile (i, j), lane (g, n), register r: S[F(4g + r) + i][F n + j];
-  // then z), into the operand slot: S^T hi parts at (row e, contraction c),
-  // z's hi parts in the even rows of the z tile and its lo parts in the odd
-  uint16_t* slot = (uint16_t*)(slots + (tile * g.H + head) * TC::SLOT);
-  for (int u = threadIdx.x; u < E; u += 256) {
-    const double sum = ((double)red[0][u] + (double)red[1][u]) + ((double)red[2][u] + (double)red[3][u]);
-    const uint16_t hi = to_bf16((float)sum);
-    if (u < D * D) {
-      const int r = u & 3, ln = (u >> 2) & 63, ij = u >> 8;
-      const int i = ij / F, j = ij % F;
-      const int c = F * (4 * (ln >> 4) + r) + i, e = F * (ln & 15) + j;
-      // T image: A[row = value feature e][k = key feature c]
-      const int rp = RB::pos(e), kp = RB::pos(c);
-      const int word = ((rp >> 2) * TC::NS + (kp >> 3)) * 64 + 16 * RB::group(c) + 4 * RB::group(e) + (rp & 3);
-      slot[word * 8 + (kp & 7)] = hi;
-      if (TC::Q4 < 8) slot[word * 8 + (kp & 7) + 4] = 0;  // d = 16: padding of the k-step
-    } else {
-      const int c = u - D * D;
-      const uint16_t lo = to_bf16((float)(sum - (double)bf16f(hi)));
-      const int kp = RB::pos(c);
-      for (int mm = 0; mm < 16; ++mm) {
-        const int word = TC::S_WORDS + (kp >> 3) * 64 + 16 * RB::group(c) + mm;
-        slot[word * 8 + (kp & 7)] = (mm & 1) ? lo : hi;
-        if (TC::Q4 < 8) slot[word * 8 + (kp & 7) + 4] = 0;
+  const int ns = nsrc;
+  // FP64 sum of the column partials, four consecutive elements per thread
+  // (16-byte loads of every partial in flight together); element u of the
+  // partial layout (tile (i, j), lane (g, n), register r: S[F(4g + r) + i]
+  // [F n + j]; then z) goes into the operand slot: S^T hi parts at (row e,
+  // contraction c), z's hi parts in the even rows of the z tile and its lo
+  // parts in the odd.  The slot is assembled in LDS (every one of its
+  // halfwords is written) and stored with whole 16-byte vectors.
+  __shared__ u32x4 simg[TC::SLOT];
+  uint16_t* slot = (uint16_t*)simg;
+  for (int u4 = threadIdx.x; u4 < E / 4; u4 += 256) {
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < ns; s0 += 9) {
+      const int cnt = min(9, ns - s0);
+      f32x4 x[9];
+#pragma unroll
+      for (int s = 0; s < 9; ++s)
+        if (s < cnt) x[s] = *(const f32x4*)(cols + src[s0 + s] + 4 * u4);
+#pragma unroll
+      for (int s = 0; s < 9; ++s)
+        if (s < cnt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sum[r] += (double)x[s][r];
+    }
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int u = 4 * u4 + r4;
+      const uint16_t hi = to_bf16((float)sum[r4]);
+      if (u < D * D) {
+        const int r = u & 3, ln = (u >> 2) & 63, ij = u >> 8;
+        const int i = ij / F, j = ij % F;
+        const int cc = F * (4 * (ln >> 4) + r) + i, e = F * (ln & 15) + j;
+        // T image: A[row = value feature e][k = key feature cc]
+        const int rp = RB::pos(e), kp = RB::pos(cc);
+        const int word = ((rp >> 2) * TC::NS + (kp >> 3)) * 64 + 16 * RB::group(cc) + 4 * RB::group(e) + (rp & 3);
+        slot[word * 8 + (kp & 7)] = hi;
+        if (TC::Q4 < 8) slot[word * 8 + (kp & 7) + 4] = 0;  // d = 16: padding of the k-step
+      } else {
+        const int cc = u - D * D;
+        const uint16_t lo = to_bf16((float)(sum[r4] - (double)bf16f(hi)));
+        const int kp = RB::pos(cc);
+        for (int mm = 0; mm < 16; ++mm) {
+          const int word = TC::S_WORDS + (kp >> 3) * 64 + 16 * RB::group(cc) + mm;
+          slot[word * 8 + (kp & 7)] = (mm & 1) ? lo : hi;
+          if (TC::Q4 < 8) slot[word * 8 + (kp & 7) + 4] = 0;
+        }
       }
     }
   }
+  __syncthreads();
+  u32x4* dst = slots + (tile * g.H + head) * TC::SLOT;
+  for (int w = threadIdx.x; w < TC::SLOT; w += 256) dst[w] = simg[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -234,7 +413,7 @@ void tile_summary_kernel(TGeo g, const void* __restrict__ k, const void* __restr
 // core / 2; its positions are covered only by tiles j - 1 and j of that
 // dimension (halo <= core / 2).  Slot s = (st, sy, sx) in {0, 1}^3 holds
 // tile (jt - 1 + st, jy - 1 + sy, jx - 1 + sx) if it exists: the S^T hi
-// parts (S_t to about 2^-9) and the hi / lo z tile.  Eight waves take the
+// parts (S_t to about 2^-9) and the hi / lo z tile.  The waves take the
 // cell's 16-token tiles (row-major over the cell) two at a time.  The
 // eight slots take 80 KiB of LDS at d = 64, so two workgroups share a
 // compute unit and one's staging overlaps the other's streaming.
@@ -475,25 +654,43 @@ la_status make_tgeo(const la_tile_desc* td, int64_t heads, TGeo* g) {
   if (td->dtype != LA_BF16) return LA_ERR_UNSUPPORTED;
   if (g->d != 16 && g->d != 32 && g->d != 64) return LA_ERR_UNSUPPORTED;
   for (int k = 0; k < 3; ++k)
-    if (2 * g->halo[k] > g->core[k]) return LA_ERR_UNSUPPORTED;  // cells need <= 2 tiles per dim
+    if (2 * g->halo[k] > g->core[k]) return LA_ERR_UNSUPPORTED;  // <= 2 tiles per dim at a point
   const int64_t field = td->dims[0] * td->dims[1] * td->dims[2];
-  // 32-bit token coordinates in the kernels; flat grids (cells >= tiles)
+  // 32-bit token coordinates in the kernels; flat grids (cells >= tiles);
+  // a tile's t extent is one FP32 run of a column partial
   if (heads > 65535 || tok > 65536 || field >= (int64_t(1) << 31) ||
-      cells * heads >= (int64_t(1) << 31))
+      cells * heads >= (int64_t(1) << 31) || g->L[0] > 16384)
     return LA_ERR_UNSUPPORTED;
   g->tile_tokens = tok;
   g->n_tiles = tiles;
   g->n_cells = cells;
-  // four FP32 partials per (tile, head), each of at most 16,384 tokens
-  const int64_t Tw = ((tok + 3) / 4 + 31) / 32 * 32;
-  if (Tw > 16384) return LA_ERR_UNSUPPORTED;
-  g->P = 4;
-  g->Tw = (int)Tw;
+  // footprint parts: a column partial sums the tile's t extent times one
+  // part of the widest segment pair's footprint, at most 16,384 tokens
+  g->ns[0] = 1;
+  int64_t wmax[3] = {0, 0, 0};
+  for (int k = 1; k < 3; ++k) {
+    g->ns[k] = 2 * g->n[k] + 1;
+    wmax[k] = std::max(2 * g->halo[k], g->core[k] - 2 * g->halo[k]);
+  }
+  const int64_t fpmax = wmax[1] * wmax[2];
+  int Pf = 1;
+  while (g->L[0] * ((fpmax + Pf - 1) / Pf) > 16384) ++Pf;
+  if (Pf > 8) return LA_ERR_UNSUPPORTED;
+  g->Pf = Pf;
+  // t chunks: enough column walks to fill the machine a few times over;
+  // each chunk re-reads the planes its first tile shares with the one
+  // before (2 halo of every CH * core)
+  const int64_t base = g->ns[1] * g->ns[2] * Pf * heads;
+  const int64_t want = std::min(g->n[0], std::max<int64_t>(1, (8192 + base - 1) / base));
+  g->CH = (g->n[0] + want - 1) / want;
+  g->nch = (g->n[0] + g->CH - 1) / g->CH;
+  g->n_items = g->nch * base;
+  if ((g->n_items + 3) / 4 >= (int64_t(1) << 31)) return LA_ERR_UNSUPPORTED;
   return LA_OK;
 }
 
 struct TLayout {
-  size_t img, total;
+  size_t img, cols, total;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -506,11 +703,14 @@ size_t slot_bytes(int64_t D) {
   }
 }
 
-// the workspace holds one operand slot per (tile, head)
+// the workspace holds one operand slot per (tile, head), then the column
+// partials (per tile row along t, segment pair, part and head)
 TLayout tlayout(const TGeo& g) {
   TLayout L{};
   L.img = 0;
-  L.total = align256((size_t)g.n_tiles * g.H * slot_bytes(g.d));
+  L.cols = align256((size_t)g.n_tiles * g.H * slot_bytes(g.d));
+  const size_t E = (size_t)(g.d * g.d + g.d);
+  L.total = L.cols + align256((size_t)g.n[0] * g.ns[1] * g.ns[2] * g.Pf * g.H * E * sizeof(float));
   return L;
 }
 
@@ -518,11 +718,18 @@ template <int D>
 hipError_t launch_tiled(const TGeo& g, const TLayout& L, const void* q, const void* k,
                         const void* v, void* o, char* ws, hipStream_t st) {
   {
-    ProfScope prof("tile_summary", st);
-    hipLaunchKernelGGL(tile_summary_kernel<D>, dim3((unsigned)(g.n_tiles * g.H)), dim3(256), 0, st,
-                       g, k, v, (u32x4*)(ws + L.img));
+    ProfScope prof("tile_cols", st);
+    hipLaunchKernelGGL(tile_cols_kernel<D>, dim3((unsigned)((g.n_items + 3) / 4)), dim3(256), 0, st,
+                       g, k, v, (float*)(ws + L.cols));
   }
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  {
+    ProfScope prof("tile_slots", st);
+    hipLaunchKernelGGL(tile_slot_kernel<D>, dim3((unsigned)(g.n_tiles * g.H)), dim3(256), 0, st,
+                       g, (const float*)(ws + L.cols), (u32x4*)(ws + L.img));
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   {
     ProfScope prof("tile_apply", st);

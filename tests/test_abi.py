@@ -237,6 +237,9 @@ def test_tiled_forward_argument_checks():
     assert ws((16, 32, 64), (4, 16, 16), (2, 8, 8), 256, 0, 3)[0] == 1    # C % heads
     assert ws((16, 32, 64), (4, 16, 16), (5, 8, 8), 256, 0, 4)[0] == 1    # halo > core
     assert ws((64, 64, 64), (64, 32, 40), (0, 0, 0), 256, 0, 4)[0] == 2   # > 65,536 tokens a tile
+    # a tile's t extent is one FP32 run of its column sums: at most 16,384
+    assert ws((16385, 1, 1), (16385, 1, 1), (0, 0, 0), 256, 0, 4)[0] == 2
+    assert ws((16384, 1, 1), (16384, 1, 1), (0, 0, 0), 256, 0, 4)[0] == 0
     # the kernels address fields with 32-bit token indices: 2^31 tokens and
     # more are refused, one fewer is accepted (nothing is allocated here)
     assert ws((2048, 1024, 1024), (8, 16, 16), (2, 4, 4), 64, 0, 4)[0] == 2

@@ -95,7 +95,12 @@ FUSED = [((2, 16, 24), (1, 8, 8), (0, 2, 3), 2, 32),     # ragged x tiles
          ((4, 9, 13), (2, 4, 5), (1, 2, 2), 3, 16),      # ragged everywhere
          ((3, 16, 32), (2, 8, 16), (1, 4, 8), 2, 64),    # halos of half a core
          ((8, 8, 16), (8, 8, 16), (0, 0, 0), 1, 64),     # one tile: global attention
-         ((5, 7, 11), (3, 3, 4), (0, 1, 2), 4, 16)]
+         ((5, 7, 11), (3, 3, 4), (0, 1, 2), 4, 16),
+         # chunks of two tiles along t (planes shared inside a chunk) with
+         # halos of half a core in t
+         ((32, 32, 32), (4, 8, 8), (2, 2, 2), 16, 16),
+         # a footprint split in two parts (FP32 runs of 16,384 tokens)
+         ((8, 64, 64), (4, 64, 64), (2, 0, 0), 1, 32)]
 
 
 @pytest.mark.parametrize("dims,core,halo,H,d", FUSED)
