@@ -506,9 +506,11 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
       load_run<D, DT_BF16>(qh + x.tk[u].off + gl * RN::CB, x.qw[u]);
     }
   };
+  // fetches past the cell's end locate its last token again (no branch
+  // around the loads); such tokens are not ok: no weight, nothing stored
   Step sa, sb;
   const int64_t base0 = (int64_t)wave * TT;
-  if (base0 < ntile) fetch(base0, sa);
+  fetch(base0, sa);
 
   // stage the covering tiles' operands (the first queries are in flight):
   // every load of a thread is issued before its LDS stores (in two rounds
@@ -621,11 +623,19 @@ void tile_apply_kernel(TGeo g, const void* __restrict__ q, void* __restrict__ o,
     }
   };
 
-  for (int64_t base = base0; base < ntile; base += 2 * per_step) {
-    if (base + per_step < ntile) fetch(base + per_step, sb);
+  // two register sets in turn.  The fetches are unconditional and the loop
+  // body has no early exit (an odd step count runs one step with nothing
+  // to weigh or store), so the compiler's wait before a step covers only
+  // that step's queries, not the next step's nor the previous outputs'
+  // stores; the scheduling barriers keep each fetch ahead of the step it
+  // overlaps
+  const int64_t nsteps = base0 < ntile ? (ntile - 1 - base0) / per_step + 1 : 0;
+  for (int64_t k = 0; k < nsteps; k += 2) {
+    fetch(base0 + (k + 1) * per_step, sb);
+    __builtin_amdgcn_sched_barrier(0);
     compute(sa);
-    if (base + per_step >= ntile) break;
-    if (base + 2 * per_step < ntile) fetch(base + 2 * per_step, sa);
+    fetch(base0 + (k + 2) * per_step, sa);
+    __builtin_amdgcn_sched_barrier(0);
     compute(sb);
   }
 }
