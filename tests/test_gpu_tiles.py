@@ -125,6 +125,40 @@ def test_fused_tiled_forward_matches_oracle_composition(dims, core, halo, H, d):
     assert normwise(as64(out).reshape(1, 1, -1), as64(unfused).reshape(1, 1, -1)) < 1e-2
 
 
+def random_geometries(count, seed):
+    # seeded ragged geometries: any grid extent from 1, cores up to the
+    # extent (ceil-divided tiles, the last one clamped), halos from 0 to
+    # half a core, 1 to 4 heads of d = 16, 32 or 64
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        dims = tuple(int(rng.integers(1, m)) for m in (7, 21, 27))
+        core = tuple(int(rng.integers(1, n + 1)) for n in dims)
+        halo = tuple(int(rng.integers(0, c // 2 + 1)) for c in core)
+        L = [c + 2 * h for c, h in zip(core, halo)]
+        if L[0] * L[1] * L[2] > 65536:
+            continue
+        out.append((dims, core, halo, int(rng.choice([1, 2, 4])), int(rng.choice([16, 32, 64]))))
+    return out
+
+
+@pytest.mark.parametrize("dims,core,halo,H,d", random_geometries(12, 2026))
+def test_fused_tiled_forward_random_geometries(dims, core, halo, H, d):
+    # the segment-pair decomposition of the tile summaries (zero-width
+    # segments when a halo is 0 or half a core, clamped border planes,
+    # extents of 1) against the oracle's extract -> attention -> blend
+    dev = require_gpu()
+    q, k, v = (field(dims, H * d, "bf16", s) for s in (61, 62, 63))
+    tq, tk, tv = (to_device(a, dev).view(*dims, H, d) for a in (q, k, v))
+    print("fused tiled (random)", dims, core, halo, H, d, flush=True)
+    out = la.tiled_forward(tq, tk, tv, core, halo)
+    torch.cuda.synchronize()
+    ref = oracle_tiled(q, k, v, dims, core, halo, H, d)
+    err = normwise(as64(out).reshape(1, 1, -1), ref.reshape(1, 1, -1))
+    print("  normwise", err, flush=True)
+    assert err < TOL["bf16"]
+
+
 def test_fused_tiled_forward_bitwise_deterministic_and_full_grid_shape():
     # the paper's per-frame 32 x 64 patch grid, 16 frames, 4 heads of d = 64
     dev = require_gpu()
