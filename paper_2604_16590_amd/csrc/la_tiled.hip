@@ -58,8 +58,9 @@ __device__ __forceinline__ uint32_t clamp32(int32_t v, int32_t hi) {
 
 // Hann weight of coordinate u of a tile extent L, sampled at cell centres:
 // w(u) = sin^2(pi (u + 1/2) / L) for 0 <= u < L (strictly positive), else
-// 0; inv2L = 1 / (2L).  The hardware sine takes its argument in revolutions (sin(2 pi x)); its
-// error (about 1e-6) is far below the bf16 rounding of the blended output.
+// 0; inv2L = 1 / (2L).  The hardware sine takes its argument in
+// revolutions (sin(2 pi x)); its error (about 1e-6) is far below the bf16
+// rounding of the blended output.
 __device__ __forceinline__ float hann_w(int32_t u, int32_t L, float inv2L) {
   const float s = __builtin_amdgcn_sinf(((float)u + 0.5f) * inv2L);
   return (u >= 0 && u < L) ? s * s : 0.f;
@@ -87,7 +88,7 @@ struct TiledCfg {
 
 // ---------------------------------------------------------------------------
 // Pass 1: the tile summaries, with phi(k) and the operand packing done once
-// per token and t-neighbourhood instead of once per covering tile.  Along
+// per token (and t chunk) instead of once per covering tile.  Along
 // y and x, tile j's extended range [jc - h, (j+1)c + h) is the union of
 // three segments: Z_j = [jc - h, jc + h) (shared with tile j - 1), I_j =
 // [jc + h, (j+1)c - h) (its own) and Z_{j+1}; numbered s = 2j (Z_j) and
