@@ -107,6 +107,9 @@ def parse():
                     help="arrivals per serving point (the 2,000-arrival window takes minutes)")
     ap.add_argument("--cpu-tokens", type=int, default=262144,
                     help="tokens per head of the oracle sample (8 heads, d = 128)")
+    ap.add_argument("--tiled-step", action="store_true",
+                    help="only time the fused tiled step (T256 x 64 x 128, 16 heads of d = 64) "
+                         "and print one JSON line (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -164,10 +167,15 @@ STEP_SOURCES = ("la_api.cpp", "la_backward.hip", "la_device.h", "la_forward.hip"
                 "la_kernels.h", "la_profile.cpp", "la_profile.h", "la_summary.h")
 
 
-def source_digest():
+# the sources of the fused tiled step's kernels
+TILED_SOURCES = ("la_device.h", "la_kernels.h", "la_profile.cpp", "la_profile.h", "la_summary.h",
+                 "la_tiled.hip")
+
+
+def source_digest(files=STEP_SOURCES):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2604_16590_amd", "csrc")
-    for f in STEP_SOURCES:
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -188,6 +196,45 @@ def traffic_for(kernel):
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+TILED_STEP = {"dims": (256, 64, 128), "core": (8, 16, 16), "halo": (2, 4, 4), "H": 16, "d": 64}
+
+
+def tiled_step_fields():
+    """Q, K, V fields [T, Y, X, H, d] of the tiled step's grid (seeded
+    synthetic bf16) and its output field."""
+    import torch
+    import paper_2604_16590_amd as la
+    t = TILED_STEP
+    qkv = []
+    for sid in range(3):
+        x = torch.empty(t["dims"] + (t["H"], t["d"]), dtype=torch.bfloat16, device="cuda:0")
+        la.gen_fill(x.view(1, 1, -1, t["H"] * t["d"]), seed=1004, stream_id=sid)
+        qkv.append(x)
+    return qkv, torch.empty_like(qkv[0])
+
+
+def tiled_step_only(steps, warmup):
+    """The fused tiled step alone (the kernels of the tiled profile)."""
+    import torch
+    import paper_2604_16590_amd as la
+    t = TILED_STEP
+    qkv, o = tiled_step_fields()
+    fused = lambda: la.tiled_forward(*qkv, t["core"], t["halo"], out=o)
+    for _ in range(warmup):
+        fused()
+    torch.cuda.synchronize()
+    la.profile_enable(True)
+    for _ in range(steps):
+        fused()
+    kst = la.profile_read()
+    la.profile_enable(False)
+    print(json.dumps({"workload": "fused tiled step, T256 x 64 x 128, cores 8 x 16 x 16, halos "
+                                  "2 x 4 x 4, 16 heads of d = 64, bf16",
+                      "steps": steps, "warmup": warmup,
+                      "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in kst.items()},
+                      "tiled_source_digest": source_digest(TILED_SOURCES)}), flush=True)
 
 
 def other_workloads(steps):
@@ -269,13 +316,7 @@ def other_workloads(steps):
     # the whole tiled step on the same grid, 16 heads of d = 64: fused
     # (la_tiled_forward: tile summaries read K, V in place, one pass reads Q
     # and writes O) against the composition that materialises the tiles
-    H, d = 16, 64
-    qkv = []
-    for sid in range(3):
-        x = torch.empty(dims + (H, d), dtype=torch.bfloat16, device="cuda:0")
-        la.gen_fill(x.view(1, 1, -1, H * d), seed=1004, stream_id=sid)
-        qkv.append(x)
-    o = torch.empty_like(qkv[0])
+    qkv, o = tiled_step_fields()
     fused = lambda: la.tiled_forward(*qkv, core, halo, out=o)
     t_f = time_steps(fused, max(steps, 10), 2)
     la.profile_enable(True)
@@ -486,9 +527,13 @@ def summarize_profiles(top, prof=None):
     for the library's plain 1 GiB copy.  The commands are the ones in
     the headers below (run from /tmp with TMPDIR=/tmp)."""
     prof = prof or os.path.join(ROOT, "profiles")
+    cal = "rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py --copy-calibration"
+    if os.path.isdir(os.path.join(top, "tiled_trace")):
+        summarize_tiled(top, prof, cal)
+    if not os.path.isdir(os.path.join(top, "trace")):
+        return
     cmd = ("rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py "
            "--steps 5 --warmup 2 --no-fp32 --no-cpu-baseline --no-serve --no-others")
-    cal = "rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py --copy-calibration"
     # kernel statistics
     rows = read_csv(find_one(os.path.join(top, "trace"), "kernel_stats.csv"))
     lines = ["# rocprofv3 kernel statistics: long-context workload (B1 H8 N2097152 d128 bf16), "
@@ -607,6 +652,84 @@ def summarize_profiles(top, prof=None):
     print("wrote profiles/ summaries (source digest %s)" % rec["source_digest"])
 
 
+# the fused tiled step's kernels (d = 64) and their algorithmic field
+# passes: K and V read by the column walks, Q read and O written by the
+# apply; the slot pass moves workspace only
+TILED_KERNELS = (("tile_cols_kernel<64>", "tile_cols", 2), ("tile_slot_kernel<64>", "tile_slots", 0),
+                 ("tile_apply_kernel<64>", "tile_apply", 2))
+
+
+def summarize_tiled(top, prof, cal):
+    """profiles/tiled_step_T256_Y64_X128_H16_d64.txt: kernel statistics
+    and HBM traffic per launch of the fused tiled step, from a kernel trace
+    and FETCH_SIZE / WRITE_SIZE runs of bench.py --tiled-step, the counters
+    scaled by the same plain-copy calibration as the long-context ones."""
+    cmd = ("rocprofv3 %s -f csv -d %s -o run -- python3 /root/repo/bench.py --tiled-step "
+           "--steps 10 --warmup 2")
+    digests = set()
+    for name in ("tiled_trace.out", "tiled_fetch.out", "tiled_write.out"):
+        path = os.path.join(top, name)
+        if os.path.isfile(path):
+            digests.add(last_json_line(path).get("tiled_source_digest"))
+    if len(digests) != 1 or None in digests:
+        raise SystemExit("the tiled runs carry no common source digest: %s" % sorted(map(str, digests)))
+    digest = digests.pop()
+    events = last_json_line(os.path.join(top, "tiled_trace.out"))["kernels_ms"]
+    rows = read_csv(find_one(os.path.join(top, "tiled_trace"), "kernel_stats.csv"))
+    durs = {}
+    for r in read_csv(find_one(os.path.join(top, "tiled_trace"), "kernel_trace.csv")):
+        durs.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    fetch = counter_means(os.path.join(top, "tiled_fetch"), "FETCH_SIZE")
+    write = counter_means(os.path.join(top, "tiled_write"), "WRITE_SIZE")
+    cf = [v for k, v in counter_means(os.path.join(top, "copy_fetch"), "FETCH_SIZE").items()
+          if COPY_KERNEL in k]
+    cw = [v for k, v in counter_means(os.path.join(top, "copy_write"), "WRITE_SIZE").items()
+          if COPY_KERNEL in k]
+    if len(cf) != 1 or len(cw) != 1:
+        raise SystemExit("copy calibration kernel not found")
+    f_fac, w_fac = float(1 << 20) / cf[0][0], float(1 << 20) / cw[0][0]
+    t = TILED_STEP
+    field = t["dims"][0] * t["dims"][1] * t["dims"][2] * t["H"] * t["d"] * 2
+    lines = ["# rocprofv3 on the fused tiled step: T256 x 64 x 128 grid, cores 8 x 16 x 16, halos "
+             "2 x 4 x 4, 16 heads of d = 64, bf16",
+             "# commands: cd /tmp && TMPDIR=/tmp " + cmd % ("--kernel-trace --stats", "DIR/tiled_trace"),
+             "#           cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc FETCH_SIZE", "DIR/tiled_fetch"),
+             "#           cd /tmp && TMPDIR=/tmp " + cmd % ("--pmc WRITE_SIZE", "DIR/tiled_write"),
+             "#           cd /tmp && TMPDIR=/tmp " + cal % ("--pmc FETCH_SIZE", "DIR/copy_fetch"),
+             "#           cd /tmp && TMPDIR=/tmp " + cal % ("--pmc WRITE_SIZE", "DIR/copy_write"),
+             "# (DIR: the rocprofv3 output directory later given to bench.py --summarize-profiles)",
+             "# sources of the tiled kernels: digest %s; counters scaled by the plain 1 GiB copy "
+             "(FETCH_SIZE factor %.4f, WRITE_SIZE factor %.4f)" % (digest, f_fac, w_fac),
+             "# alg_GB: the field passes the kernel must make (K, V read; Q read, O written); "
+             "bench_avg_ms: the library's HIP-event timer in the traced run",
+             "%-11s %6s %10s %10s %13s %12s %12s %13s %13s %9s" % (
+                 "kernel", "calls", "avg_ms", "median_ms", "bench_avg_ms", "fetch_KiB", "write_KiB",
+                 "hbm_GB/launch", "alg_GB/launch", "alg_GB/s")]
+    total_ms = 0.0
+    for key, pname, passes in TILED_KERNELS:
+        row = [r for r in rows if key in r["Name"]]
+        if len(row) != 1:
+            raise SystemExit("kernel %s not found once in the tiled trace" % key)
+        row = row[0]
+        fk = [v for k, v in fetch.items() if key in k]
+        wk = [v for k, v in write.items() if key in k]
+        fk = fk[0][0] if fk else 0.0
+        wk = wk[0][0] if wk else 0.0
+        avg = float(row["AverageNs"]) / 1e6
+        med = sorted(durs[row["Name"]])[len(durs[row["Name"]]) // 2] / 1e6
+        total_ms += med
+        alg = passes * field
+        lines.append("%-11s %6s %10.4f %10.4f %13s %12.0f %12.0f %13.3f %13.3f %9s" % (
+            pname, row["Calls"], avg, med, events.get(pname, "-"), fk, wk,
+            (fk * f_fac + wk * w_fac) * 1024.0 / 1e9, alg / 1e9,
+            "%.1f" % (alg / (med * 1e-3) / 1e9) if alg else "-"))
+    lines.append("step (sum of medians) %.4f ms: %.2f GB of field passes, %.1f GB/s, %.4f of 8 TB/s"
+                 % (total_ms, 4 * field / 1e9, 4 * field / (total_ms * 1e-3) / 1e9,
+                    4 * field / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS))
+    with open(os.path.join(prof, "tiled_step_T256_Y64_X128_H16_d64.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 MFMA_COUNTERS = "SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES"
 
 
@@ -711,6 +834,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.tiled_step:
+        tiled_step_only(args.steps, args.warmup)
+        return
 
     if args.copy_calibration:
         # the library's plain copy (stream_copy_swept_kernel): reads and

@@ -106,3 +106,54 @@ def test_profile_summaries_from_rocprof_csv(tmp_path):
     import pytest
     with pytest.raises(SystemExit):
         bench.summarize_profiles(str(top), str(out))
+
+
+def test_tiled_profile_summary_from_rocprof_csv(tmp_path):
+    # the fused tiled step's summary: kernel statistics (the median launch
+    # from the trace), counters scaled by the copy calibration, the field
+    # passes of each kernel and the step's rate over the sum of medians
+    import bench
+    top = tmp_path / "prof"
+    names = {"cols": "void la::(anonymous namespace)::tile_cols_kernel<64>(la::TGeo, ...)",
+             "slots": "void la::(anonymous namespace)::tile_slot_kernel<64>(la::TGeo, ...)",
+             "apply": "void la::(anonymous namespace)::tile_apply_kernel<64>(la::TGeo, ...)"}
+    ms = {"cols": 2.0, "slots": 0.4, "apply": 2.4}
+    _write_csv(str(top / "tiled_trace" / "run_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs",
+                "StdDev"],
+               [[names[k], 3, ms[k] * 3e6, ms[k] * 1e6, 30.0, 1, 1, 0] for k in names])
+    trace = []
+    for k in names:
+        for i, f in enumerate((1.5, 1.0, 1.0)):   # one slow first launch; median = ms[k]
+            trace.append([names[k], 1000 * i, 1000 * i + int(ms[k] * f * 1e6)])
+    _write_csv(str(top / "tiled_trace" / "run_kernel_trace.csv"),
+               ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
+    _write_csv(str(top / "tiled_fetch" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("FETCH_SIZE", [(names["cols"], [4.0e6]), (names["apply"], [2.0e6])]))
+    _write_csv(str(top / "tiled_write" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("WRITE_SIZE", [(names["cols"], [1.0e6]), (names["apply"], [4.0e6])]))
+    _write_csv(str(top / "copy_fetch" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("FETCH_SIZE", [(COPY, [524288.0])]))
+    _write_csv(str(top / "copy_write" / "run_counter_collection.csv"), COUNTER_HEADER,
+               _counter_rows("WRITE_SIZE", [(COPY, [1048576.0])]))
+    line = {"kernels_ms": {"tile_cols": 2.01, "tile_slots": 0.41, "tile_apply": 2.41},
+            "tiled_source_digest": bench.source_digest(bench.TILED_SOURCES)}
+    for name in ("tiled_trace.out", "tiled_fetch.out", "tiled_write.out"):
+        (top / name).write_text(json.dumps(line) + "\n")
+    out = tmp_path / "profiles"
+    out.mkdir()
+    bench.summarize_profiles(str(top), str(out))   # no long-context runs in DIR: tiled only
+    text = open(out / "tiled_step_T256_Y64_X128_H16_d64.txt").read()
+    field = 256 * 64 * 128 * 16 * 64 * 2
+    rows = {l.split()[0]: l.split() for l in text.splitlines() if l.startswith("tile_")}
+    assert rows["tile_cols"][3] == "2.0000"                         # median launch
+    assert float(rows["tile_cols"][7]) == round((4.0e6 * 2 + 1.0e6) * 1024 / 1e9, 3)
+    assert float(rows["tile_cols"][8]) == round(2 * field / 1e9, 3)
+    assert rows["tile_slots"][9] == "-"                             # workspace only
+    assert "step (sum of medians) 4.8000 ms" in text
+    assert not (out / "counters_long_context_bf16.json").exists()
+    # runs on other sources are refused
+    (top / "tiled_write.out").write_text(json.dumps(dict(line, tiled_source_digest="other")) + "\n")
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.summarize_profiles(str(top), str(out))
