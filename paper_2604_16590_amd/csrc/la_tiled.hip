@@ -187,9 +187,10 @@ __device__ __forceinline__ void col_step(const SummaryRegs<DT_BF16, D, MODE_FWD>
 
 // 1a. grid: four waves per workgroup, each its own item; items ordered
 // head fastest, so the waves reading one token row's head slices run side
-// by side.  One wave per SIMD: at d = 64 the two tiles' sums, the two
-// register sets of tokens and the operands take about 256 registers (two
-// waves per SIMD spilled and ran 5 % slower)
+// by side.  The bound of one wave per SIMD lets the compiler keep the two
+// tiles' sums in the accumulation registers: at d = 64 it takes 242
+// registers in all, so two waves per SIMD still run; held to two waves per
+// SIMD it kept them in the vector registers and spilled (5 % slower)
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
 void tile_cols_kernel(TGeo g, const void* __restrict__ k, const void* __restrict__ v,
@@ -229,27 +230,24 @@ void tile_cols_kernel(TGeo g, const void* __restrict__ k, const void* __restrict
   const uint32_t neg_inf = 0xff80ff80u;
   // the step js of plane t: lane group gq takes footprint positions
   // p0 + STEP*js + R*gq + r; 32-bit coordinates (a field holds fewer
-  // than 2^31 tokens)
-  auto load = [&](int32_t t, uint32_t js, Regs& x) {
+  // than 2^31 tokens).  Every load is issued: positions past the part's
+  // end are clamped into the grid like all others, and the step drops
+  // them (bit r of the lane's mask is clear), so no branch stands between
+  // a step's loads and the compiler's count of them
+  auto load = [&](int32_t t, uint32_t js, Regs& x, uint32_t& mask) {
     const uint32_t j = p0 + STEP * js + R * gq;
     uint32_t uy = j / xw;
     uint32_t ux = j - uy * xw;
     const uint32_t gt = clamp32(t, M0);
-    const bool full = p0 + STEP * (js + 1) <= p1;  // wave-uniform
+    mask = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (full || j + r < p1) {
-        const uint32_t gy = clamp32(ys + (int32_t)uy, M1);
-        const uint32_t gx = clamp32(xs + (int32_t)ux, M2);
-        const int64_t off = (int64_t)((gt * N1 + gy) * N2 + gx) * rowb;
-        load_words<C::KB>(kb + off, x.kw[r]);
-        load_words<C::VB>(vb + off, x.vw[r]);
-      } else {
-#pragma unroll
-        for (int w = 0; w < C::KW; ++w) x.kw[r][w] = neg_inf;
-#pragma unroll
-        for (int w = 0; w < C::VW; ++w) x.vw[r][w] = 0;
-      }
+      mask |= (uint32_t)(j + r < p1) << r;
+      const uint32_t gy = clamp32(ys + (int32_t)uy, M1);
+      const uint32_t gx = clamp32(xs + (int32_t)ux, M2);
+      const int64_t off = (int64_t)((gt * N1 + gy) * N2 + gx) * rowb;
+      load_words<C::KB>(kb + off, x.kw[r]);
+      load_words<C::VB>(vb + off, x.vw[r]);
       if (++ux == xw) {
         ux = 0;
         ++uy;
@@ -270,7 +268,18 @@ void tile_cols_kernel(TGeo g, const void* __restrict__ k, const void* __restrict
     }
   }
   int64_t a = a0;  // the tile whose sum is ac; an is tile a + 1's
-  auto process = [&](const Regs& x, int32_t t, uint32_t js) {
+  auto process = [&](Regs& x, uint32_t mask, int32_t t, uint32_t js) {
+    if (p0 + STEP * (js + 1) > p1) {  // a part's last, partial step (wave-uniform)
+      // dropped positions: phi(-inf) = 0 and v = 0 add nothing
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool keep = (mask >> r) & 1u;
+#pragma unroll
+        for (int w = 0; w < C::KW; ++w) x.kw[r][w] = keep ? x.kw[r][w] : neg_inf;
+#pragma unroll
+        for (int w = 0; w < C::VW; ++w) x.vw[r][w] = keep ? x.vw[r][w] : 0u;
+      }
+    }
     const int32_t next_first = (int32_t)(a + 1) * c0 - h0;  // tile a + 1's first plane
     col_step<D>(x, a + 1 < a1 && t >= next_first, ac, zc, an, zn);
     if (js == spp - 1 && t == next_first + 2 * h0 - 1) {  // tile a's last plane done
@@ -312,17 +321,20 @@ void tile_cols_kernel(TGeo g, const void* __restrict__ k, const void* __restrict
     if (lt != t_stop - 1 || ljs != spp - 1) advance(lt, ljs);
   };
   Regs ra, rb;
-  load(lt, ljs, ra);
+  uint32_t ma, mb;
+  load(lt, ljs, ra, ma);
   advance_load();
   for (int64_t s = 0; s < total; s += 2) {
-    load(lt, ljs, rb);
+    load(lt, ljs, rb, mb);
     advance_load();
-    process(ra, ct, cjs);
+    __builtin_amdgcn_sched_barrier(0);
+    process(ra, ma, ct, cjs);
     advance(ct, cjs);
-    load(lt, ljs, ra);
+    load(lt, ljs, ra, ma);
     advance_load();
+    __builtin_amdgcn_sched_barrier(0);
     if (s + 1 < total) {
-      process(rb, ct, cjs);
+      process(rb, mb, ct, cjs);
       advance(ct, cjs);
     }
   }
