@@ -100,7 +100,10 @@ FUSED = [((2, 16, 24), (1, 8, 8), (0, 2, 3), 2, 32),     # ragged x tiles
          # halos of half a core in t
          ((32, 32, 32), (4, 8, 8), (2, 2, 2), 16, 16),
          # a footprint split in two parts (FP32 runs of 16,384 tokens)
-         ((8, 64, 64), (4, 64, 64), (2, 0, 0), 1, 32)]
+         ((8, 64, 64), (4, 64, 64), (2, 0, 0), 1, 32),
+         # cores larger than the grid: one tile per dimension, its extended
+         # range clamped on both sides
+         ((3, 5, 7), (4, 8, 8), (2, 2, 4), 2, 16)]
 
 
 @pytest.mark.parametrize("dims,core,halo,H,d", FUSED)
